@@ -1,0 +1,244 @@
+"""ctypes wrapper of the CPU oracle (test infrastructure only).
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may import this package.
+The rasterizer library never loads it; the two share no code.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+class _Mesh(C.Structure):
+    _fields_ = [("pos", C.c_void_p), ("V", C.c_uint32), ("idx", C.c_void_p), ("T", C.c_uint64),
+                ("inst", C.c_void_p), ("N", C.c_uint32)]
+
+
+class _View(C.Structure):
+    _fields_ = [("vp", C.c_float * 16), ("near_plane", C.c_float), ("width", C.c_int32),
+                ("height", C.c_int32)]
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b  # noqa: F401  (oracle/build.py)
+            _b.build()
+        _lib = C.CDLL(_LIB_PATH)
+        P = C.c_void_p
+        _lib.orc_num_pairs.restype = C.c_int64
+        _lib.orc_num_pairs.argtypes = [P, C.c_uint32]
+        for name, args in {
+            "orc_id_bases": [P, C.c_uint32, P],
+            "orc_decode_id": [P, C.c_uint32, P, C.c_int64, P, P, P],
+            "orc_rasterize": [P, C.c_uint32, P, P, C.c_int],
+            "orc_rasterize_masked": [P, C.c_uint32, P, P, P, C.c_int],
+            "orc_rasterize_range": [P, C.c_uint32, P, C.c_int64, C.c_int64, C.c_uint64, C.c_uint64, P, C.c_int],
+            "orc_coverage_counts": [P, C.c_uint32, P, P, P],
+            "orc_rasterize_brute": [P, C.c_uint32, P, P],
+            "orc_project": [P, C.c_uint32, P, P],
+            "orc_resolve": [P, C.c_uint32, P, P, P, C.c_uint32, P, C.c_int],
+            "orc_resolve_screen": [P, C.c_int32, C.c_int32, P, C.c_uint64, C.c_int64, P, C.c_uint32, P, C.c_uint32, P],
+            "orc_resolve_screen_f64": [P, C.c_int32, C.c_int32, P, C.c_uint64, C.c_int64, P, C.c_uint32, P, C.c_uint32, P],
+            "orc_resolve_screen_backward_f64": [P, C.c_int32, C.c_int32, P, C.c_uint64, C.c_int64, P, C.c_uint32, P,
+                                                C.c_uint32, P, P, P],
+            "orc_fd_pos_grad_l2": [P, C.c_int32, C.c_int32, P, C.c_uint64, C.c_int64, P, C.c_uint32, P, C.c_uint32,
+                                   P, P, C.c_uint32, C.c_double, C.c_int, P],
+        }.items():
+            f = getattr(_lib, name)
+            f.restype = C.c_int
+            f.argtypes = args
+    return _lib
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+class _Pack:
+    """Keeps numpy arrays alive while their pointers sit in ctypes structures."""
+
+    def __init__(self, meshes, view=None):
+        self.keep = []
+        arr = (_Mesh * max(1, len(meshes)))()
+        for i, m in enumerate(meshes):
+            pos = np.ascontiguousarray(m.pos, np.float32)
+            idx = np.ascontiguousarray(m.idx, np.uint32)
+            inst = None if m.inst is None else np.ascontiguousarray(m.inst, np.float32)
+            self.keep += [pos, idx, inst]
+            arr[i] = _Mesh(pos.ctypes.data, pos.shape[0], idx.ctypes.data, idx.shape[0],
+                           None if inst is None else inst.ctypes.data, 1 if inst is None else inst.shape[0])
+        self.meshes = arr
+        self.M = len(meshes)
+        if view is not None:
+            v = _View()
+            vp = np.ascontiguousarray(view.vp, np.float32).reshape(16)
+            for k in range(16):
+                v.vp[k] = float(vp[k])
+            v.near_plane = float(view.near)
+            v.width = int(view.width)
+            v.height = int(view.height)
+            self.view = v
+
+
+def _check(rc, name):
+    if rc != 0:
+        raise RuntimeError(f"oracle {name} failed with {rc}")
+
+
+def id_bases(meshes) -> np.ndarray:
+    pk = _Pack(meshes)
+    n = lib().orc_num_pairs(pk.meshes, pk.M)
+    out = np.zeros(n + 1, np.int64)
+    _check(lib().orc_id_bases(pk.meshes, pk.M, out.ctypes.data), "id_bases")
+    return out
+
+
+def decode_id(meshes, bases: np.ndarray, gid: int):
+    pk = _Pack(meshes)
+    m, i, t = C.c_uint32(), C.c_uint32(), C.c_uint64()
+    rc = lib().orc_decode_id(pk.meshes, pk.M, bases.ctypes.data, int(gid), C.byref(m), C.byref(i), C.byref(t))
+    return None if rc != 0 else (m.value, i.value, t.value)
+
+
+def rasterize(meshes, view, threads: int = 0) -> np.ndarray:
+    pk = _Pack(meshes, view)
+    vis = np.empty((view.height, view.width), np.uint64)
+    _check(lib().orc_rasterize(pk.meshes, pk.M, C.byref(pk.view), vis.ctypes.data, threads), "rasterize")
+    return vis
+
+
+def rasterize_masked(meshes, view, mask: np.ndarray, threads: int = 0) -> np.ndarray:
+    pk = _Pack(meshes, view)
+    mask = np.ascontiguousarray(mask, np.uint8)
+    vis = np.empty((view.height, view.width), np.uint64)
+    _check(lib().orc_rasterize_masked(pk.meshes, pk.M, C.byref(pk.view), mask.ctypes.data, vis.ctypes.data,
+                                      threads), "rasterize_masked")
+    return vis
+
+
+def rasterize_range(meshes, view, pair_begin: int, pair_end: int, tri_begin: int, tri_end: int,
+                    threads: int = 0) -> np.ndarray:
+    pk = _Pack(meshes, view)
+    vis = np.empty((view.height, view.width), np.uint64)
+    _check(lib().orc_rasterize_range(pk.meshes, pk.M, C.byref(pk.view), pair_begin, pair_end, tri_begin,
+                                     tri_end, vis.ctypes.data, threads), "rasterize_range")
+    return vis
+
+
+def rasterize_brute(meshes, view) -> np.ndarray:
+    pk = _Pack(meshes, view)
+    vis = np.empty((view.height, view.width), np.uint64)
+    _check(lib().orc_rasterize_brute(pk.meshes, pk.M, C.byref(pk.view), vis.ctypes.data), "rasterize_brute")
+    return vis
+
+
+def coverage_counts(meshes, view):
+    pk = _Pack(meshes, view)
+    front = np.empty((view.height, view.width), np.uint32)
+    back = np.empty((view.height, view.width), np.uint32)
+    _check(lib().orc_coverage_counts(pk.meshes, pk.M, C.byref(pk.view), front.ctypes.data, back.ctypes.data),
+           "coverage_counts")
+    return front, back
+
+
+def project(mesh, view, instance: int = 0) -> np.ndarray:
+    pk = _Pack([mesh], view)
+    out = np.empty((mesh.pos.shape[0], 3), np.float32)
+    _check(lib().orc_project(C.byref(pk.meshes[0]), instance, C.byref(pk.view), out.ctypes.data), "project")
+    return out
+
+
+def resolve(meshes, view, vis: np.ndarray, attrs: Sequence[np.ndarray], threads: int = 0) -> np.ndarray:
+    pk = _Pack(meshes, view)
+    C_ = int(attrs[0].shape[1])
+    keep = [np.ascontiguousarray(a, np.float32) for a in attrs]
+    ptrs = (C.c_void_p * len(keep))(*[a.ctypes.data for a in keep])
+    vis = np.ascontiguousarray(vis, np.uint64)
+    out = np.empty((view.height, view.width, C_), np.float32)
+    _check(lib().orc_resolve(pk.meshes, pk.M, C.byref(pk.view), vis.ctypes.data, ptrs, C_, out.ctypes.data,
+                             threads), "resolve")
+    return out
+
+
+def resolve_screen(vis, idx, id_base, pos_ss, attrs) -> np.ndarray:
+    H, W = vis.shape
+    vis = np.ascontiguousarray(vis, np.uint64)
+    idx = np.ascontiguousarray(idx, np.uint32)
+    pos_ss = np.ascontiguousarray(pos_ss, np.float32)
+    attrs = np.ascontiguousarray(attrs, np.float32)
+    out = np.empty((H, W, attrs.shape[1]), np.float32)
+    _check(lib().orc_resolve_screen(vis.ctypes.data, W, H, idx.ctypes.data, idx.shape[0], int(id_base),
+                                    pos_ss.ctypes.data, pos_ss.shape[0], attrs.ctypes.data, attrs.shape[1],
+                                    out.ctypes.data), "resolve_screen")
+    return out
+
+
+def resolve_screen_f64(vis, idx, id_base, pos_ss, attrs) -> np.ndarray:
+    H, W = vis.shape
+    vis = np.ascontiguousarray(vis, np.uint64)
+    idx = np.ascontiguousarray(idx, np.uint32)
+    pos_ss = np.ascontiguousarray(pos_ss, np.float64)
+    attrs = np.ascontiguousarray(attrs, np.float64)
+    out = np.empty((H, W, attrs.shape[1]), np.float64)
+    _check(lib().orc_resolve_screen_f64(vis.ctypes.data, W, H, idx.ctypes.data, idx.shape[0], int(id_base),
+                                        pos_ss.ctypes.data, pos_ss.shape[0], attrs.ctypes.data, attrs.shape[1],
+                                        out.ctypes.data), "resolve_screen_f64")
+    return out
+
+
+def resolve_screen_backward_f64(vis, idx, id_base, pos_ss, attrs, grad_out):
+    H, W = vis.shape
+    vis = np.ascontiguousarray(vis, np.uint64)
+    idx = np.ascontiguousarray(idx, np.uint32)
+    pos_ss = np.ascontiguousarray(pos_ss, np.float64)
+    attrs = np.ascontiguousarray(attrs, np.float64)
+    grad_out = np.ascontiguousarray(grad_out, np.float64)
+    ga = np.zeros(attrs.shape, np.float64)
+    gp = np.zeros(pos_ss.shape, np.float64)
+    _check(lib().orc_resolve_screen_backward_f64(vis.ctypes.data, W, H, idx.ctypes.data, idx.shape[0],
+                                                 int(id_base), pos_ss.ctypes.data, pos_ss.shape[0],
+                                                 attrs.ctypes.data, attrs.shape[1], grad_out.ctypes.data,
+                                                 ga.ctypes.data, gp.ctypes.data), "resolve_backward_f64")
+    return ga, gp
+
+
+def fd_pos_grad_l2(vis, idx, id_base, pos_ss, attrs, target, verts, eps=1e-3, order4=True) -> np.ndarray:
+    H, W = vis.shape
+    vis = np.ascontiguousarray(vis, np.uint64)
+    idx = np.ascontiguousarray(idx, np.uint32)
+    pos_ss = np.ascontiguousarray(pos_ss, np.float64)
+    attrs = np.ascontiguousarray(attrs, np.float64)
+    target = np.ascontiguousarray(target, np.float64)
+    verts = np.ascontiguousarray(verts, np.uint32)
+    fd = np.zeros((verts.shape[0], 3), np.float64)
+    _check(lib().orc_fd_pos_grad_l2(vis.ctypes.data, W, H, idx.ctypes.data, idx.shape[0], int(id_base),
+                                    pos_ss.ctypes.data, pos_ss.shape[0], attrs.ctypes.data, attrs.shape[1],
+                                    target.ctypes.data, verts.ctypes.data, verts.shape[0], float(eps),
+                                    1 if order4 else 0, fd.ctypes.data), "fd_pos_grad_l2")
+    return fd
+
+
+# ----------------------------------------------------------------------------------------------
+# Key layout helpers (Sec. 4.1: 28-bit depth above a 36-bit global triangle ID)
+# ----------------------------------------------------------------------------------------------
+EMPTY = np.uint64(0xFFFFFFFFFFFFFFFF)
+ID_BITS = 36
+
+
+def key_id(vis: np.ndarray) -> np.ndarray:
+    return vis & np.uint64((1 << ID_BITS) - 1)
+
+
+def key_depth(vis: np.ndarray) -> np.ndarray:
+    """float32 depth with the 3 dropped mantissa bits zeroed (valid where vis != EMPTY)."""
+    d28 = (vis >> np.uint64(ID_BITS)).astype(np.uint32)
+    return (d28 << np.uint32(3)).view(np.float32)

@@ -1,0 +1,474 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics (CPU only).
+
+Each test is chosen so that a plausible mistake in the oracle (a dropped term, a wrong sign or
+index, a transposed operand, a wrong tie rule, an off-by-one bound) fails at least one of them:
+
+  * brute force vs bounding-box traversal (two independent transcriptions, bit for bit)
+  * hand-derived golden triangle: exact covered set, exact key (Sec. 4.1 layout), exact resolve
+  * projection closed form (Sec. 4.1 Eqs. 1-2)
+  * watertightness: closed sphere winding invariant, camera inside a closed box (clip path),
+    planar grid covers its rectangle exactly once
+  * depth: exact powers of two for fronto-parallel triangles, fp64 closed form for tilted ones
+  * tie-break by triangle ID, key layout, ID prefix-sum decode
+  * clip path vs an fp64 analytic coverage of the visible part
+  * resolve vs the paper's world-space ray/plane formulation (Sec. 4.4) and constant attributes
+  * backward: partition of unity, linearity in the attributes, fp64 analytic vs central FD
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2604_21749_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _view_cam(width, height, fovy=90.0, near=0.01, eye=(0.0, 0.0, 0.0), target=(0.0, 0.0, -1.0)):
+    return W.View(W.camera(eye, target, fovy_deg=fovy, aspect=width / height), near, width, height)
+
+
+def _ids(vis):
+    return O.key_id(vis)
+
+
+# ----------------------------------------------------------------------------------------------
+# brute force
+# ----------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("variant", [
+    {}, {"snap_grid": True}, {"near_crossing": True}, {"n_instances": 3}, {"spread": 8.0},
+    {"near_crossing": True, "spread": 6.0, "n_tris": 24},
+])
+def test_brute_force_matches_bbox_traversal(variant):
+    for seed in range(25):
+        s = W.random_tiny_scene(seed, **variant)
+        a = O.rasterize(s.meshes, s.views[0], threads=3)
+        b = O.rasterize_brute(s.meshes, s.views[0])
+        assert np.array_equal(a, b), (seed, variant)
+
+
+def test_brute_force_scenes_exercise_ties_and_clipping():
+    """The brute-force comparison is only a pin if its inputs reach the tie and clip cases."""
+    ties = 0
+    for seed in range(25):
+        s = W.random_tiny_scene(seed, snap_grid=True)
+        ss = O.project(s.meshes[0], s.views[0])
+        frac = ss[:, :2] * 2.0
+        ties += int(np.sum(frac == np.round(frac)))
+    assert ties > 100
+    behind = 0
+    for seed in range(25):
+        s = W.random_tiny_scene(seed, near_crossing=True)
+        ss = O.project(s.meshes[0], s.views[0])
+        behind += int(np.sum(ss[:, 2] < s.views[0].near))
+    assert behind > 20
+
+
+# ----------------------------------------------------------------------------------------------
+# golden fixtures
+# ----------------------------------------------------------------------------------------------
+def _golden_triangle_scene(g, pad=True):
+    verts = np.array(g["vertices"], np.float32)
+    npad = g["pad_triangles_before"] if pad else 0
+    far = np.array([[0, 0, -5], [0.01, 0, -5], [0, 0.01, -5]], np.float32)  # tiny, covers nothing
+    pos = np.concatenate([far] * npad + [verts]) if npad else verts
+    idx = np.arange(pos.shape[0], dtype=np.uint32).reshape(-1, 3)
+    attrs = np.zeros((pos.shape[0], 3), np.float32)
+    attrs[-3:] = np.array(g["resolve_attrs"], np.float32)
+    mesh = W.Mesh(pos, idx, attrs=attrs)
+    view = _view_cam(g["width"], g["height"], fovy=g["fovy_deg"], near=g["near"])
+    return mesh, view
+
+
+def test_golden_single_triangle():
+    g = json.load(open(os.path.join(GOLDEN, "single_triangle.json")))
+    mesh, view = _golden_triangle_scene(g)
+    vis = O.rasterize([mesh], view)
+    py, px = np.mgrid[0:g["height"], 0:g["width"]]
+    expect = (px >= 2) & (py >= 2) & (px + py <= 10)
+    assert int(expect.sum()) == g["expected_covered_count"]
+    assert np.array_equal(vis != O.EMPTY, expect)
+    assert np.all(vis[expect] == np.uint64(int(g["expected_key_hex"], 16)))
+    out = O.resolve([mesh], view, vis, [mesh.attrs])
+    x, y = g["resolve_pixel"]
+    assert out[y, x].tolist() == g["resolve_expected"]
+
+
+def test_golden_projection_cases():
+    g = json.load(open(os.path.join(GOLDEN, "projection_cases.json")))
+    for case in g["cases"]:
+        view = _view_cam(case["width"], case["height"], fovy=case["fovy_deg"])
+        mesh = W.Mesh(np.array([case["view_point"]], np.float32), np.zeros((0, 3), np.uint32))
+        ss = O.project(mesh, view)
+        assert ss[0].tolist() == case["expected"], case
+
+
+def test_projection_matches_paper_closed_form():
+    """Sec. 4.1: x_ndc = x f/(aspect d), y_ndc = y f/d, depth = d for view point (x, y, -d)."""
+    rng = np.random.default_rng(5)
+    for fovy, Wd, Hd in [(60.0, 640, 480), (45.0, 333, 517), (100.0, 1920, 1080)]:
+        view = _view_cam(Wd, Hd, fovy=fovy)
+        d = rng.uniform(0.05, 50.0, 200)
+        p = np.stack([rng.uniform(-1, 1, 200) * d, rng.uniform(-1, 1, 200) * d, -d], 1).astype(np.float32)
+        mesh = W.Mesh(p, np.zeros((0, 3), np.uint32))
+        ss = O.project(mesh, view).astype(np.float64)
+        f = 1.0 / math.tan(math.radians(fovy) / 2)
+        a = Wd / Hd
+        P = p.astype(np.float64)
+        ex = (P[:, 0] * f / (a * -P[:, 2]) + 1.0) * Wd / 2
+        ey = (P[:, 1] * f / -P[:, 2] + 1.0) * Hd / 2
+        # a few binary32 roundings of values of magnitude up to ~2 * size
+        assert np.all(np.abs(ss[:, 0] - ex) <= 8 * 2.0 ** -23 * 2 * Wd)
+        assert np.all(np.abs(ss[:, 1] - ey) <= 8 * 2.0 ** -23 * 2 * Hd)
+        assert np.all(np.abs(ss[:, 2] + P[:, 2]) <= 4 * 2.0 ** -23 * d)
+
+
+# ----------------------------------------------------------------------------------------------
+# watertightness
+# ----------------------------------------------------------------------------------------------
+def _jittered_sphere(lat, lon, seed, sigma):
+    pos, idx = W.uv_sphere(lat, lon, 1.0)
+    rng = np.random.default_rng(seed)
+    pos = (pos.astype(np.float64) + rng.normal(0, sigma, pos.shape)).astype(np.float32)
+    return W.Mesh(pos, idx)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_closed_sphere_front_equals_back(seed):
+    """For a closed surface seen from outside, every pixel centre is entered as often as it is
+    left: #front == #back exactly, under any consistent fill rule of exact integer edges."""
+    rng = np.random.default_rng(100 + seed)
+    sphere = _jittered_sphere(24, 48, seed, 4e-3)
+    d = rng.uniform(2.2, 6.0)
+    direction = rng.normal(size=3)
+    direction /= np.linalg.norm(direction)
+    Wd, Hd = int(rng.integers(40, 90)), int(rng.integers(40, 90))
+    view = W.View(W.camera(direction * d, (0, 0, 0), aspect=Wd / Hd), 0.01, Wd, Hd)
+    front, back = O.coverage_counts([sphere], view)
+    assert np.array_equal(front, back)
+    # the silhouette is (nearly) the disk of angular radius asin(1/d)
+    f = 1.0 / math.tan(math.radians(60.0) / 2)
+    r_px = f * math.tan(math.asin(1.0 / d)) * Hd / 2
+    area = math.pi * r_px ** 2
+    assert abs(int((front > 0).sum()) - area) < 0.1 * area + 2 * math.pi * r_px
+
+
+def _box(half=1.0):
+    p = np.array([[x, y, z] for x in (-half, half) for y in (-half, half) for z in (-half, half)], np.float32)
+    # outward-facing, counter-clockwise seen from outside
+    q = [(0, 1, 3, 2), (4, 6, 7, 5), (0, 4, 5, 1), (2, 3, 7, 6), (0, 2, 6, 4), (1, 5, 7, 3)]
+    tris = []
+    for a, b, c, d in q:
+        tris += [(a, b, c), (a, c, d)]
+    return p, np.array(tris, np.uint32)
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_camera_inside_closed_box_sees_each_pixel_once(seed):
+    """Clip path pin: from inside a closed box every view ray leaves through exactly one face,
+    so after near-plane and guard-band clipping every pixel centre is covered exactly once, by a
+    back-facing fragment.  Fails on any crack or overlap along clipped shared edges."""
+    rng = np.random.default_rng(200 + seed)
+    p, t = _box(1.0)
+    X = W.instance_matrices(W.random_rotations(rng, 1), np.array([rng.uniform(0.5, 4.0)]),
+                            rng.uniform(-0.2, 0.2, (1, 3)))
+    mesh = W.Mesh(p, t, inst=X)
+    Wd, Hd = int(rng.integers(30, 80)), int(rng.integers(30, 80))
+    target = rng.normal(size=3)
+    view = W.View(W.camera((0, 0, 0), target, fovy_deg=float(rng.uniform(40, 120)), aspect=Wd / Hd),
+                  float(rng.uniform(0.001, 0.2)), Wd, Hd)
+    front, back = O.coverage_counts([mesh], view)
+    assert np.all(front == 0)
+    assert np.all(back == 1)
+
+
+def test_planar_grid_covers_rectangle_exactly_once():
+    """A flat grid facing the camera at depth 2 covers every pixel centre of its window
+    rectangle [x0, x1) x (y0, y1] exactly once (left and top borders are top-left edges)."""
+    Wd = Hd = 64
+    view = _view_cam(Wd, Hd)       # fovy 90: view (x, y, -2) -> window (16x + 32, 16y + 32)
+    x0, x1, y0, y1 = 5.5, 52.25, 9.0, 50.5           # window rectangle, exact in binary32
+    n = 7
+    gx = np.linspace(x0, x1, n + 1)
+    gy = np.linspace(y0, y1, n + 1)
+    gx = np.round(gx * 256) / 256
+    gy = np.round(gy * 256) / 256
+    vx, vy = np.meshgrid((gx - 32) / 16, (gy - 32) / 16)
+    pos = np.stack([vx.ravel(), vy.ravel(), np.full(vx.size, -2.0)], 1).astype(np.float32)
+    tris = []
+    for r in range(n):
+        for c in range(n):
+            a, b, cc, d = r * (n + 1) + c, r * (n + 1) + c + 1, (r + 1) * (n + 1) + c, (r + 1) * (n + 1) + c + 1
+            tris += [(a, b, d), (a, d, cc)] if (r + c) % 2 else [(a, b, cc), (b, d, cc)]
+    mesh = W.Mesh(pos, np.array(tris, np.uint32))
+    front, back = O.coverage_counts([mesh], view)
+    cy, cx = np.mgrid[0:Hd, 0:Wd] + 0.5
+    expect = (cx >= x0) & (cx < x1) & (cy > y0) & (cy <= y1)
+    assert np.array_equal(front, expect.astype(np.uint32))
+    assert np.all(back == 0)
+    vis = O.rasterize([mesh], view)
+    assert np.array_equal(vis != O.EMPTY, expect)
+    assert np.all(O.key_depth(vis[expect]) == 2.0)
+
+
+# ----------------------------------------------------------------------------------------------
+# depth
+# ----------------------------------------------------------------------------------------------
+def test_fronto_parallel_depth_is_exact():
+    """Equal 1/w at the three vertices: every partial sum of the depth denominator is exact when
+    area < 2^24, so the depth is exactly the plane depth (here powers of two)."""
+    rng = np.random.default_rng(7)
+    view = _view_cam(96, 64, fovy=70.0)
+    for k in range(-3, 6):
+        d = 2.0 ** k
+        pos = []
+        for _ in range(20):
+            c = rng.uniform(-0.5, 0.5, 2) * d
+            for _v in range(3):
+                pos.append([c[0] + rng.uniform(-0.12, 0.12) * d, c[1] + rng.uniform(-0.12, 0.12) * d, -d])
+        pos = np.array(pos, np.float32)
+        idx = np.arange(pos.shape[0], dtype=np.uint32).reshape(-1, 3)
+        idx = np.concatenate([idx, idx[:, [0, 2, 1]]])          # both windings, one of them visible
+        vis = O.rasterize([W.Mesh(pos, idx)], view)
+        cov = vis != O.EMPTY
+        assert cov.sum() > 20
+        assert np.all(O.key_depth(vis[cov]) == np.float32(d)), k
+
+
+def test_tilted_plane_depth_matches_fp64():
+    """Depth of a tilted triangle at each covered pixel centre vs the fp64 perspective-correct
+    depth over the snapped window triangle (interpolated 1/w): agreement to the 3 dropped
+    mantissa bits plus a few roundings."""
+    view = _view_cam(64, 64)               # view (x, y, -z) -> window (32x/z + 32, 32y/z + 32)
+    # window positions on the 1/256 grid and power-of-two depths make the snapped inputs exact
+    win = np.array([[3.25, 4.0], [60.5, 10.75], [20.0, 58.5]])
+    z = np.array([1.0, 4.0, 2.0])
+    pos = np.stack([(win[:, 0] - 32) / 32 * z, (win[:, 1] - 32) / 32 * z, -z], 1).astype(np.float32)
+    vis = O.rasterize([W.Mesh(pos, np.array([[0, 1, 2]], np.uint32))], view)
+    cov = vis != O.EMPTY
+    assert cov.sum() > 500
+    py, px = np.nonzero(cov)
+    cx, cy = px + 0.5, py + 0.5
+    (x0, y0), (x1, y1), (x2, y2) = win
+    area = (x1 - x0) * (y2 - y0) - (y1 - y0) * (x2 - x0)
+    e0 = (x2 - x1) * (cy - y1) - (y2 - y1) * (cx - x1)
+    e1 = (x0 - x2) * (cy - y2) - (y0 - y2) * (cx - x2)
+    e2 = (x1 - x0) * (cy - y0) - (y1 - y0) * (cx - x0)
+    depth = area / (e0 / z[0] + e1 / z[1] + e2 / z[2])
+    got = O.key_depth(vis[cov]).astype(np.float64)
+    rel = (depth - got) / depth
+    assert np.all(rel >= -4 * 2.0 ** -24)            # truncation only lowers the value
+    assert np.all(rel <= 2.0 ** -20 + 4 * 2.0 ** -24)
+
+
+# ----------------------------------------------------------------------------------------------
+# key, tie-break, IDs
+# ----------------------------------------------------------------------------------------------
+def test_tie_break_prefers_smaller_id_and_key_layout():
+    s = W.random_tiny_scene(11, n_tris=12)
+    m = s.meshes[0]
+    dup = W.Mesh(m.pos, np.concatenate([m.idx, m.idx]))           # IDs t and t + 12 coincide
+    vis = O.rasterize([dup], s.views[0])
+    cov = vis != O.EMPTY
+    assert cov.sum() > 100
+    assert np.all(_ids(vis[cov]) < 12)
+    # same via two identical instances: instance 0's IDs win
+    ident = np.array([[1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]] * 2, np.float32)
+    vis2 = O.rasterize([W.Mesh(m.pos, m.idx, inst=ident)], s.views[0])
+    assert np.array_equal(vis2, O.rasterize([m], s.views[0]))
+    # layout: depth in bits 36..63 (28 bits: float bits without the sign bit and the 3 lowest
+    # mantissa bits), a finite positive depth, never the clear value
+    d = O.key_depth(vis[cov])
+    assert np.all(d > 0) and np.all(np.isfinite(d))
+    assert np.all((vis[cov] >> np.uint64(36)) <= np.uint64(0x0FEFFFFF))
+    assert not np.any(vis[cov] == O.EMPTY)
+
+
+def test_id_prefix_and_binary_search_round_trip():
+    rng = np.random.default_rng(3)
+    meshes = []
+    for T, N in [(5, 1), (0, 3), (7, 4), (1, 1), (0, 1), (13, 2)]:
+        pos = rng.normal(size=(4, 3)).astype(np.float32)
+        idx = rng.integers(0, 4, (T, 3)).astype(np.uint32)
+        inst = None if N == 1 else np.tile(np.eye(3, 4, dtype=np.float32).reshape(1, 12), (N, 1))
+        meshes.append(W.Mesh(pos, idx, inst=inst))
+    bases = O.id_bases(meshes)
+    expect = []
+    for mi, m in enumerate(meshes):
+        for i in range(m.num_instances):
+            for t in range(m.num_triangles):
+                expect.append((mi, i, t))
+    assert bases[-1] == len(expect)
+    for gid, e in enumerate(expect):
+        assert O.decode_id(meshes, bases, gid) == e
+    assert O.decode_id(meshes, bases, len(expect)) is None
+
+
+# ----------------------------------------------------------------------------------------------
+# clip path vs fp64 analytic coverage
+# ----------------------------------------------------------------------------------------------
+def _analytic_cover(tri_view, width, height, fovy, near, margin_px):
+    """fp64: clip the view-space triangle to depth >= near, project, test pixel centres against
+    the resulting convex polygon; returns (covered, decided) where decided excludes centres
+    within margin_px of an edge."""
+    f = 1.0 / math.tan(math.radians(fovy) / 2)
+    a = width / height
+    poly = [np.array(v, np.float64) for v in tri_view]
+    out = []
+    for i in range(len(poly)):
+        p, q = poly[i], poly[(i + 1) % len(poly)]
+        dp, dq = -p[2] - near, -q[2] - near
+        if dp >= 0:
+            out.append(p)
+        if (dp >= 0) != (dq >= 0):
+            t = dp / (dp - dq)
+            out.append(p + t * (q - p))
+    win = np.array([[(v[0] * f / (a * -v[2]) + 1) * width / 2, (v[1] * f / -v[2] + 1) * height / 2] for v in out])
+    cy, cx = np.mgrid[0:height, 0:width] + 0.5
+    inside = np.ones((height, width), bool)
+    mind = np.full((height, width), np.inf)
+    n = len(win)
+    orient = 0.0
+    for i in range(n):
+        orient += win[i][0] * win[(i + 1) % n][1] - win[(i + 1) % n][0] * win[i][1]
+    sgn = 1.0 if orient > 0 else -1.0
+    for i in range(n):
+        p, q = win[i], win[(i + 1) % n]
+        e = q - p
+        L = math.hypot(*e)
+        if L == 0:
+            continue
+        dist = sgn * (e[0] * (cy - p[1]) - e[1] * (cx - p[0])) / L
+        inside &= dist > 0
+        mind = np.minimum(mind, np.abs(dist))
+    return inside & (orient > 0), mind > margin_px
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_clipped_triangle_matches_fp64_coverage(seed):
+    rng = np.random.default_rng(300 + seed)
+    Wd, Hd, fovy, near = 64, 48, 75.0, 0.05
+    view = _view_cam(Wd, Hd, fovy=fovy, near=near)
+    while True:
+        tri = np.stack([rng.uniform(-3, 3, 3), rng.uniform(-3, 3, 3), -rng.uniform(-2.0, 4.0, 3)], 1)
+        if np.sum(-tri[:, 2] < near) in (1, 2):
+            break
+    tri32 = tri.astype(np.float32)
+    tri = tri32.astype(np.float64)
+    for order in ([0, 1, 2], [0, 2, 1]):
+        mesh = W.Mesh(tri32, np.array([order], np.uint32))
+        front, back = O.coverage_counts([mesh], view)
+        cov, decided = _analytic_cover(tri[order], Wd, Hd, fovy, near, 0.02)
+        vis = O.rasterize([mesh], view)
+        assert np.array_equal((vis != O.EMPTY), front > 0)
+        assert np.array_equal(front[decided] > 0, cov[decided]), order
+        assert np.all(front + back <= 1)
+
+
+# ----------------------------------------------------------------------------------------------
+# resolve
+# ----------------------------------------------------------------------------------------------
+def test_resolve_constant_attribute():
+    s = W.scene_c1()
+    vis = O.rasterize(s.meshes, s.views[0])
+    consts = [np.full_like(m.attrs, 0.37) for m in s.meshes]
+    out = O.resolve(s.meshes, s.views[0], vis, consts)
+    cov = vis != O.EMPTY
+    assert np.all(out[~cov] == 0)
+    assert np.max(np.abs(out[cov] - np.float32(0.37))) <= 16 * 2.0 ** -24
+
+
+def test_resolve_matches_world_space_ray_hit():
+    """Sec. 4.4 shades in world space: cast the pixel's ray, intersect the triangle's plane and
+    interpolate there.  An attribute affine in world position must therefore resolve to that
+    affine function at the ray hit."""
+    rng = np.random.default_rng(9)
+    eye = np.array([0.3, 1.2, 2.5])
+    target = np.array([0.0, 0.0, 0.0])
+    Wd, Hd = 80, 60
+    view = W.View(W.camera(eye, target, aspect=Wd / Hd), 0.01, Wd, Hd)
+    # random front-facing triangles near the origin
+    pos = rng.uniform(-0.8, 0.8, (30, 3)).astype(np.float32)
+    idx = np.arange(30, dtype=np.uint32).reshape(10, 3)
+    G = np.array([[0.3, -0.2, 0.5], [0.1, 0.4, -0.3], [-0.6, 0.2, 0.2]])
+    off = np.array([0.7, 0.2, 0.4])
+    attrs = (pos.astype(np.float64) @ G.T + off).astype(np.float32)
+    mesh = W.Mesh(pos, np.concatenate([idx, idx[:, [0, 2, 1]]]), attrs=attrs)
+    vis = O.rasterize([mesh], view)
+    out = O.resolve([mesh], view, vis, [attrs])
+    vp = view.vp.astype(np.float64)
+    inv = np.linalg.inv(np.stack([vp[0], vp[1], vp[3], [0, 0, 0, 1]]))
+    cov = np.argwhere(vis != O.EMPTY)
+    assert len(cov) > 300
+    worst = 0.0
+    for py, px in cov:
+        t = int(O.key_id(vis[py, px]))
+        tri = pos[mesh.idx[t]].astype(np.float64)
+        # ray through the pixel centre: world points with clip (ndc_x * w, ndc_y * w, w)
+        ndc = np.array([(px + 0.5) / Wd * 2 - 1, (py + 0.5) / Hd * 2 - 1])
+        p1 = inv @ np.array([ndc[0], ndc[1], 1.0, 1.0])
+        p2 = inv @ np.array([2 * ndc[0], 2 * ndc[1], 2.0, 1.0])
+        d = p2[:3] - p1[:3]
+        nrm = np.cross(tri[1] - tri[0], tri[2] - tri[0])
+        s = np.dot(nrm, tri[0] - p1[:3]) / np.dot(nrm, d)
+        hit = p1[:3] + s * d
+        expect = G @ hit + off
+        err = np.abs(out[py, px] - expect) / np.maximum(np.abs(expect), 0.1)
+        worst = max(worst, float(err.max()))
+    assert worst < 1e-5
+
+
+# ----------------------------------------------------------------------------------------------
+# backward
+# ----------------------------------------------------------------------------------------------
+def _small_diff_scene():
+    s = W.scene_c5(n=64)
+    view = W.View(s.views[0].vp, s.views[0].near, 96, 96)
+    m = s.meshes[0]
+    vis = O.rasterize([m], view)
+    pss = O.project(m, view)
+    return m, view, vis, pss
+
+
+def test_backward_attribute_gradient_partition_of_unity_and_linearity():
+    m, view, vis, pss = _small_diff_scene()
+    rng = np.random.default_rng(1)
+    g = rng.normal(size=(view.height, view.width, 3))
+    ga, _ = O.resolve_screen_backward_f64(vis, m.idx, 0, pss, m.attrs, g)
+    cov = vis != O.EMPTY
+    # sum_k b_k = 1 at every pixel, so the total attribute gradient equals the total upstream gradient
+    assert np.allclose(ga.sum(0), g[cov].sum(0), rtol=1e-10, atol=1e-9)
+    # the output is linear in the attributes: directional derivative is exact
+    da = rng.normal(size=m.attrs.shape)
+    o1 = O.resolve_screen_f64(vis, m.idx, 0, pss, m.attrs.astype(np.float64) + da)
+    o0 = O.resolve_screen_f64(vis, m.idx, 0, pss, m.attrs.astype(np.float64))
+    assert np.isclose(np.sum(g * (o1 - o0)), np.sum(ga * da), rtol=1e-9)
+
+
+def test_backward_position_gradient_matches_central_fd():
+    m, view, vis, pss = _small_diff_scene()
+    rng = np.random.default_rng(2)
+    target = rng.normal(0.5, 0.1, (view.height, view.width, 3))
+    out = O.resolve_screen_f64(vis, m.idx, 0, pss, m.attrs)
+    cov = vis != O.EMPTY
+    g = np.where(cov[..., None], 2.0 * (out - target), 0.0)
+    _, gp = O.resolve_screen_backward_f64(vis, m.idx, 0, pss, m.attrs, g)
+    used = np.unique(m.idx[O.key_id(vis[cov]).astype(np.int64)])
+    verts = rng.choice(used, 64, replace=False).astype(np.uint32)
+    # fourth-order central stencil: its truncation error (eps^4) is far below the tolerance even
+    # for the sliver triangles a dense height field produces
+    fd = O.fd_pos_grad_l2(vis, m.idx, 0, pss, m.attrs, target, verts, eps=1e-4, order4=True)
+    ana = gp[verts]
+    scale = np.maximum(np.abs(fd), 1e-3 * np.sqrt(np.mean(fd ** 2)))
+    assert np.all(np.abs(ana - fd) <= 1e-5 * scale)
+    # the plain two-point difference converges to the same values at second order
+    fd2 = O.fd_pos_grad_l2(vis, m.idx, 0, pss, m.attrs, target, verts, eps=1e-5, order4=False)
+    assert np.all(np.abs(ana - fd2) <= 1e-4 * scale)
+    # a perturbation of the whole vector agrees with the directional derivative
+    dp = rng.normal(size=pss.shape) * 1e-4
+    lp = np.sum(np.where(cov[..., None], O.resolve_screen_f64(vis, m.idx, 0, pss + dp, m.attrs) - target, 0) ** 2)
+    lm = np.sum(np.where(cov[..., None], O.resolve_screen_f64(vis, m.idx, 0, pss - dp, m.attrs) - target, 0) ** 2)
+    assert np.isclose((lp - lm) / 2, np.sum(gp * dp), rtol=1e-5)
