@@ -1,0 +1,253 @@
+/*
+ * curast: brute-force visibility-buffer rasterization of dense, opaque, unstructured triangle
+ * meshes on one AMD Instinct MI355X (gfx950), after CuRast (Schuetz, Lipp, Kristmann, Wimmer).
+ *
+ * The library builds no acceleration structure and no level of detail.  Every triangle of every
+ * mesh instance is transformed, culled and rasterized into a 64-bit visibility buffer with a
+ * 64-bit atomic minimum on (depth28 << 36 | global triangle ID) (Sec. 3.1, Sec. 4.1): small
+ * triangles one per GPU lane (stage 1), medium ones one per wavefront (stage 2), large ones per
+ * 64x64 screen tile (stage 3, Sec. 4.1-4.3).  A resolve pass turns the IDs into perspective-
+ * correct interpolated vertex attributes (Sec. 4.4); its backward pass gives gradients with
+ * respect to the attributes and the screen-space vertex positions.
+ *
+ * Result definition (what every entry point computes exactly, whatever the stage thresholds,
+ * workgroup sizes, queue capacities or culling switches):
+ *   - draw matrix A = VP * X (rows x, y and w of the view-projection VP, row 2 unused) per
+ *     (mesh, instance), in binary32 with the operation order
+ *       A[r][c] = (VP[r][0]*X[0][c] + VP[r][1]*X[1][c]) + VP[r][2]*X[2][c]              (c < 3)
+ *       A[r][3] = ((VP[r][0]*X[0][3] + VP[r][1]*X[1][3]) + VP[r][2]*X[2][3]) + VP[r][3];
+ *   - vertex x, y, w = fmaf(A[r][0], vx, fmaf(A[r][1], vy, fmaf(A[r][2], vz, A[r][3]))); w is the
+ *     positive linear view depth (Sec. 4.1 Eqs. 1-2 are the special case of a look-at view and
+ *     the projection vector [f/aspect, f, -1]);
+ *   - triangles with every w < near produce nothing; triangles with any w < near or |x| > 16 w
+ *     or |y| > 16 w are clipped (Sutherland-Hodgman, Sec. 4.2) against w >= near and the guard
+ *     band |x|, |y| <= 16 w, intersections computed from the inside vertex, and fanned;
+ *   - window position snapped to 1/256 pixel: zI = 1/w (correctly rounded), sx = fmaf(x*zI,
+ *     W/2, W/2), X = rint(256*sx) (round half to even), and the same for y with H/2;
+ *   - a pixel (px, py) (row 0 at the bottom) is covered when its centre lies inside the snapped
+ *     triangle under int64 edge functions with the top-left rule; counter-clockwise triangles
+ *     are front-facing, back-facing and degenerate ones cover nothing (Sec. 4.1 backface cull);
+ *   - depth = area / (E0/w0 + E1/w1 + E2/w2) (interpolated 1/w, Sec. 4.1), key =
+ *     (float bits of depth >> 3) << 36 | ID, visibility buffer = per-pixel minimum key, empty
+ *     pixels all ones (0xFFFFFFFFFFFFFFFF);
+ *   - global ID = exclusive prefix of triangle counts over all (mesh, instance) pairs in
+ *     mesh-major order, plus the triangle index (Sec. 4, Sec. 4.4).
+ *
+ * Conventions for every entry point:
+ *   - All functions return CURAST_OK (0) or a negative curast_status.  Argument errors are
+ *     detected before any work is enqueued; nothing is enqueued on error.  No C++ exception
+ *     crosses this boundary.  curast_last_error() describes the last failure of a context.
+ *   - "device" pointers are HIP device allocations (e.g. torch CUDA tensor data pointers) owned
+ *     by the caller; they must stay valid until the enqueued work has completed.  "host"
+ *     pointers are read before the call returns.  The library never frees caller memory.
+ *   - `stream` is a hipStream_t (NULL = the null stream).  Work is enqueued asynchronously;
+ *     results are ready when the stream reaches that point.
+ *   - A context owns its scratch (queues, counters, descriptor staging, graph cache) and binds
+ *     to the HIP device that was current at curast_create.  Use one context per host thread;
+ *     calls on one context must not overlap on different streams.
+ *   - Vertex coordinates and matrices must be finite; width and height lie in [1, 16384];
+ *     near > 0.  Indices >= the vertex count make their triangle produce nothing.
+ */
+#ifndef CURAST_H
+#define CURAST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CURAST_OK = 0,
+    CURAST_E_INVALID = -1,      /* null pointer, bad size, width/height/near out of range */
+    CURAST_E_ID_RANGE = -2,     /* sum of triangle-instances exceeds the 36-bit ID space */
+    CURAST_E_OOM = -3,          /* device or pinned host allocation failed */
+    CURAST_E_HIP = -4,          /* a HIP runtime call failed (see curast_last_error) */
+    CURAST_E_UNSUPPORTED = -5   /* feature not available on this device */
+} curast_status;
+
+/* Option flags. */
+#define CURAST_FLAG_NO_TINY_CULL  0x1u  /* keep triangles whose bbox holds no pixel centre
+                                           (result unchanged; Sec. 4.1, Table 4) */
+#define CURAST_FLAG_NO_EARLY_OUT  0x2u  /* always issue the atomic even if the stored key is smaller */
+#define CURAST_FLAG_NO_MESH_CULL  0x4u  /* skip the host bounding-sphere frustum cull */
+#define CURAST_FLAG_STATS         0x8u  /* count per-stage events (slower; read with curast_get_stats) */
+#define CURAST_FLAG_NO_GRAPH      0x10u /* batched calls launch kernels directly instead of a hipGraph */
+#define CURAST_FLAG_TIMING        0x20u /* record HIP events around every stage (curast_get_stage_times) */
+#define CURAST_FLAG_ZERO_QUEUES   0x80000000u /* testing aid: run with stage queues of capacity 0, so
+                                                 every forwarded triangle takes the overflow paths */
+
+/* Tuning knobs; 0 selects the default (or the autotuned value).  None of them changes results. */
+typedef struct {
+    uint32_t small_px;          /* stage-1 limit on pixel centres in the clamped bbox (default 128, Sec. 4) */
+    uint32_t medium_px;         /* stage-2 limit (default 4096, Sec. 4) */
+    uint32_t s1_block;          /* stage-1 workgroup size: 64, 128, 256 or 512 (default 256, Sec. 4.1) */
+    uint32_t s1_tris_per_thread;/* triangles per thread per stage-1 work item: 1, 2 or 4 (default 1) */
+    uint32_t s1_draws_per_item; /* (instance x view) draws per stage-1 work item (default 64, Sec. 4.5) */
+    uint32_t s2_waves;          /* persistent stage-2 wavefronts (default 4 per CU) */
+    uint32_t s3_blocks;         /* persistent stage-3 workgroups (default 2 per CU) */
+    uint32_t q2_capacity;       /* stage-1 -> stage-2 queue entries (default 1M); overflow is
+                                   rasterized in place, never dropped */
+    uint32_t q3_capacity;       /* stage-2 -> stage-3 tile parts (default 1M); overflow as above */
+    uint32_t large_capacity;    /* large (sub-)triangle records for stage 3 (default 256K) */
+    uint32_t flags;             /* CURAST_FLAG_* */
+} curast_options;
+
+typedef struct {
+    const float* vertices;      /* device [V][3] object-space positions */
+    uint32_t num_vertices;      /* V */
+    const uint32_t* indices;    /* device [T][3] vertex indices */
+    uint64_t num_triangles;     /* T (at most 2^32 - 1) */
+    const float* instances;     /* host [N][12] row-major 3x4 object-to-world matrices, or NULL
+                                   for one identity instance */
+    uint32_t num_instances;     /* N (ignored when instances is NULL) */
+    float bsphere[4];           /* object-space bounding sphere (cx, cy, cz, r) containing every
+                                   vertex, used for the host frustum cull; r <= 0: unknown */
+} curast_mesh;
+
+typedef struct {
+    float view_proj[16];        /* host, row-major; rows 0, 1, 3 give clip x, y and w */
+    float near_plane;           /* > 0, in the units of w */
+    int32_t width, height;      /* pixels, 1..16384 */
+    uint64_t* visbuffer;        /* device [height][width], row 0 at the bottom */
+} curast_view;
+
+typedef struct {
+    uint64_t tri_draws;         /* triangle x instance x view items submitted after the mesh cull */
+    uint64_t draws_culled;      /* (mesh, instance, view) draws removed by the host cull */
+    uint64_t culled_near;       /* all three vertices behind the near plane */
+    uint64_t culled_frustum;    /* all vertices outside one side of the view */
+    uint64_t culled_tiny;       /* bbox holds no pixel centre (Sec. 4.1, Table 4) */
+    uint64_t culled_backface;   /* snapped area <= 0 */
+    uint64_t s1_rasterized;     /* triangles rasterized in stage 1 */
+    uint64_t q2_entries;        /* triangles forwarded to stage 2 (high-water mark of the queue) */
+    uint64_t q2_overflow;       /* forwarded triangles that did not fit and were rasterized in place */
+    uint64_t s2_rasterized;     /* (sub-)triangles rasterized in stage 2 */
+    uint64_t q3_entries;        /* tile parts forwarded to stage 3 */
+    uint64_t q3_overflow;       /* (sub-)triangles stage 2 rasterized itself because stage 3 was full */
+    uint64_t fragments;         /* covered pixel samples */
+    uint64_t atomics;           /* 64-bit atomic minimums issued (the rest skipped by the early-out) */
+} curast_stats;
+
+typedef struct curast_ctx curast_ctx;
+
+/* Create a context on the current HIP device.  opt may be NULL (all defaults).
+   Errors: CURAST_E_INVALID (out NULL or an option out of range), CURAST_E_OOM, CURAST_E_HIP. */
+int curast_create(const curast_options* opt, curast_ctx** out);
+
+/* Destroy a context after its enqueued work has completed.  NULL is accepted. */
+int curast_destroy(curast_ctx* ctx);
+
+/* Replace / read the context options (same validation as curast_create). */
+int curast_set_options(curast_ctx* ctx, const curast_options* opt);
+int curast_get_options(const curast_ctx* ctx, curast_options* opt);
+
+/*
+ * Rasterize one mesh (optionally instanced, Sec. 4.5) into one view: the call shape of the paper's
+ * frame (host cull + mesh list + stages 1-3, Sec. 4).  Clears `visbuffer` first.
+ *   vertices  device [V][3]; indices device [T][3]; instances host [N][12] or NULL;
+ *   view_proj host [16] row-major; visbuffer device [height][width].
+ * Errors: CURAST_E_INVALID, CURAST_E_ID_RANGE (T * N >= 2^36), CURAST_E_HIP.
+ */
+int curast_rasterize(curast_ctx* ctx, const float* vertices, uint32_t num_vertices,
+                     const uint32_t* indices, uint64_t num_triangles, const float* instances,
+                     uint32_t num_instances, const float view_proj[16], float near_plane,
+                     int32_t width, int32_t height, uint64_t* visbuffer, void* stream);
+
+/*
+ * Rasterize a list of meshes (Sec. 4: host-side mesh list with per-mesh/instance triangle-count
+ * prefix sums) into one view.  meshes: host array of M descriptors.  Clears the view's buffer.
+ */
+int curast_rasterize_meshes(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M,
+                            const curast_view* view, void* stream);
+
+/*
+ * Rasterize the same meshes into n_views views of independent sizes and cameras in one
+ * persistent launch sequence (captured once into a hipGraph and replayed; Sec. 4.1 persistent
+ * work loop and Sec. 4.5 instancing loop, extended over views).  Each stage-1 lane loads a
+ * triangle once and draws it for every (instance, view) that survived the host cull.  Every
+ * view's buffer equals what curast_rasterize_meshes would produce for it alone; IDs are shared.
+ * views: host array; each visbuffer a distinct device allocation.
+ */
+int curast_rasterize_batched(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M,
+                             const curast_view* views, uint32_t n_views, void* stream);
+
+/*
+ * Unsnapped window positions of one mesh instance for a view: pos_ss device [V][3] =
+ * (sx, sy, w) with sx = fmaf(x*zI, W/2, W/2), sy likewise, zI = 1/w: the rasterizer's values
+ * before the rounding to 1/256 pixel.
+ * These are the differentiable inputs of curast_resolve_screen / curast_resolve_backward.
+ */
+int curast_project(curast_ctx* ctx, const curast_mesh* mesh, uint32_t instance,
+                   const curast_view* view, float* pos_ss, void* stream);
+
+/*
+ * Resolve a view's visibility buffer into interpolated attributes (Sec. 4.4): per pixel decode
+ * the 36-bit ID, binary-search the (mesh, instance) in the int64 prefix of triangle counts,
+ * recompute the three vertices and interpolate perspective-correctly at the pixel centre.
+ *   attrs: host array of M device pointers, mesh m's per-vertex attributes [V_m][C];
+ *   out: device [height][width][C] float; empty pixels get 0.  1 <= C <= 16.
+ */
+int curast_resolve(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* view,
+                   const float* const* attrs, uint32_t C, float* out, void* stream);
+
+/*
+ * Resolve one mesh from explicit screen positions (the differentiable form):
+ *   visbuffer device [H][W]; indices device [T][3]; pos_ss device [V][3] (sx, sy, w);
+ *   attrs device [V][C]; out device [H][W][C].  Pixels whose ID is outside
+ *   [id_base, id_base + T) (other meshes, empty) get 0.  Same arithmetic as curast_resolve.
+ */
+int curast_resolve_screen(curast_ctx* ctx, const uint64_t* visbuffer, int32_t width, int32_t height,
+                          const uint32_t* indices, uint64_t num_triangles, uint64_t id_base,
+                          const float* pos_ss, uint32_t num_vertices, const float* attrs, uint32_t C,
+                          float* out, void* stream);
+
+/*
+ * Backward of curast_resolve_screen with visibility held fixed: for every covered pixel,
+ * scatter-add grad_out through the barycentrics into grad_attr [V][C] and, through the
+ * barycentrics' dependence on (sx, sy, w) of the three vertices, into grad_pos [V][3].
+ * Gradients are ACCUMULATED with float atomics (the caller zeroes them); grad_pos may be NULL.
+ * The accumulation order is not deterministic (float addition is not associative).
+ */
+int curast_resolve_backward(curast_ctx* ctx, const uint64_t* visbuffer, int32_t width, int32_t height,
+                            const uint32_t* indices, uint64_t num_triangles, uint64_t id_base,
+                            const float* pos_ss, uint32_t num_vertices, const float* attrs, uint32_t C,
+                            const float* grad_out, float* grad_attr, float* grad_pos, void* stream);
+
+/*
+ * Pick stage thresholds, workgroup sizes, work-item sizes and queue capacities for this scene
+ * by timing candidates with HIP events (coordinate descent over a fixed grid, Sec. 4's
+ * "experimentally determined" thresholds made automatic).  Results never change outputs.
+ * The chosen options are applied to ctx, returned in `chosen` (may be NULL) and, when
+ * cache_path is not NULL, stored in a JSON file keyed by device and scene class; an existing
+ * entry for the same key is loaded instead of measuring.  views' visbuffers are overwritten.
+ */
+int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* views,
+                    uint32_t n_views, const char* cache_path, curast_options* chosen, void* stream);
+
+/* Statistics accumulated since the last reset (needs CURAST_FLAG_STATS; synchronizes ctx's work). */
+int curast_get_stats(curast_ctx* ctx, curast_stats* out);
+int curast_reset_stats(curast_ctx* ctx);
+
+/* Stage durations accumulated over frames run with CURAST_FLAG_TIMING, measured with HIP events
+   on the launch stream (synchronizes those events): ms[0..7] = clear, stage 1, stage-1 overflow
+   pass, stage 2, stage 3, resolve (either form), resolve backward, whole frame; *frames = number
+   of rasterized frames timed.  Batched (graph) frames contribute only the whole-frame time. */
+int curast_get_stage_times(curast_ctx* ctx, double ms[8], uint64_t* frames);
+int curast_reset_stage_times(curast_ctx* ctx);
+
+/* Exclusive prefix of triangle counts over all (mesh, instance) pairs (host only, no GPU):
+   bases host [pairs + 1]; returns the number of pairs (>= 0) or a negative status. */
+int64_t curast_id_bases(const curast_mesh* meshes, uint32_t M, int64_t* bases);
+
+/* Static description of a status code; the last error message of a context (never NULL). */
+const char* curast_status_string(int status);
+const char* curast_last_error(const curast_ctx* ctx);
+
+/* Library version as an integer (major * 10000 + minor * 100 + patch). */
+int curast_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CURAST_H */

@@ -1,0 +1,526 @@
+// Rasterization kernels for gfx950: clear, stage 1 (one lane per small triangle), the stage-1
+// overflow pass, stage 2 (one wavefront per medium triangle, clipping) and stage 3 (one workgroup
+// per 64x64 tile part of a large triangle).  Sec. 4.1-4.3 describe the three stages; the wave64
+// mapping, ballot-compacted queues and in-place overflow handling are this implementation's.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace curast {
+
+// ----------------------------------------------------------------------------------------------
+// Statistics (compiled in only for the STATS variants)
+// ----------------------------------------------------------------------------------------------
+template <bool ON>
+struct StatAcc {
+    uint32_t v[kNumStats];
+    __device__ StatAcc()
+    {
+        for (int i = 0; i < kNumStats; ++i) v[i] = 0;
+    }
+    __device__ void add(int i, uint32_t n = 1) { v[i] += n; }
+    __device__ void flush(unsigned long long* out)
+    {
+        for (int i = 0; i < kNumStats; ++i) {
+            uint32_t s = v[i];
+            for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+            if ((threadIdx.x & 63) == 0 && s) atomicAdd(out + i, (unsigned long long)s);
+        }
+    }
+};
+
+template <>
+struct StatAcc<false> {
+    __device__ void add(int, uint32_t = 1) {}
+    __device__ void flush(unsigned long long*) {}
+};
+
+__device__ __forceinline__ uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// Number of set bits of `mask` below this lane.
+__device__ __forceinline__ uint32_t rank_in(unsigned long long mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Wave-aggregated append: one 64-bit atomic per wavefront reserves slots for every lane with
+// `want`, each lane writes its entry at base + its rank among the wanting lanes.  Must be called
+// by all lanes of the wavefront.  Returns the slot (or ~0 when the lane did not append).
+__device__ __forceinline__ unsigned long long wave_reserve(bool want, unsigned long long* counter)
+{
+    const unsigned long long mask = __ballot(want);
+    if (mask == 0) return ~0ull;
+    const uint32_t leader = __ffsll((long long)mask) - 1;
+    unsigned long long base = 0;
+    if (lane_id() == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
+    base = __shfl(base, leader);
+    return want ? base + rank_in(mask) : ~0ull;
+}
+
+// ----------------------------------------------------------------------------------------------
+// Stage-1 classification of one triangle under one draw (shared by stage 1 and its overflow pass)
+// ----------------------------------------------------------------------------------------------
+enum Route : int { kRouteNone = 0, kRouteSmall = 1, kRouteForward = 2 };
+
+struct SmallTri {
+    int32_t X[3], Y[3];
+    float zI[3];
+    int32_t px0, px1, py0, py1;
+    int32_t area;
+};
+
+template <bool STATS>
+__device__ __forceinline__ int classify(const Clip c[3], const ViewDesc& V, uint32_t small_px, bool tiny_cull,
+                                        SmallTri& s, StatAcc<STATS>& st)
+{
+    const float n = V.near_plane;
+    if (c[0].w < n && c[1].w < n && c[2].w < n) {
+        st.add(kStCulledNear);
+        return kRouteNone;
+    }
+    if (outside_guard(c[0], n) || outside_guard(c[1], n) || outside_guard(c[2], n)) return kRouteForward;
+    // all vertices beyond one side of the view: no pixel centre can be covered (the half-pixel
+    // between the view border and the first centre absorbs every rounding of the projection)
+    if ((c[0].x > c[0].w && c[1].x > c[1].w && c[2].x > c[2].w) ||
+        (c[0].x < -c[0].w && c[1].x < -c[1].w && c[2].x < -c[2].w) ||
+        (c[0].y > c[0].w && c[1].y > c[1].w && c[2].y > c[2].w) ||
+        (c[0].y < -c[0].w && c[1].y < -c[1].w && c[2].y < -c[2].w)) {
+        st.add(kStCulledFrustum);
+        return kRouteNone;
+    }
+    for (int k = 0; k < 3; ++k) snap_vertex(c[k], V.hW, V.hH, s.X[k], s.Y[k], s.zI[k]);
+    const int32_t minX = min(s.X[0], min(s.X[1], s.X[2])), maxX = max(s.X[0], max(s.X[1], s.X[2]));
+    const int32_t minY = min(s.Y[0], min(s.Y[1], s.Y[2])), maxY = max(s.Y[0], max(s.Y[1], s.Y[2]));
+    s.px0 = max(first_centre(minX), 0);
+    s.px1 = min(last_centre(maxX), V.W - 1);
+    s.py0 = max(first_centre(minY), 0);
+    s.py1 = min(last_centre(maxY), V.H - 1);
+    const bool empty = s.px0 > s.px1 || s.py0 > s.py1;
+    if (empty && tiny_cull) {
+        st.add(kStCulledTiny);
+        return kRouteNone;
+    }
+    if (maxX - minX >= kSmallExtent || maxY - minY >= kSmallExtent) return kRouteForward;
+    const int32_t cnt = empty ? 0 : (s.px1 - s.px0 + 1) * (s.py1 - s.py0 + 1);
+    if (cnt > (int32_t)small_px) return kRouteForward;
+    // extents < 2^15: the products fit 24-bit multiplies and the area fits int32
+    s.area = __mul24(s.X[1] - s.X[0], s.Y[2] - s.Y[0]) - __mul24(s.Y[1] - s.Y[0], s.X[2] - s.X[0]);
+    if (s.area <= 0) {
+        st.add(kStCulledBack);
+        return kRouteNone;
+    }
+    return kRouteSmall;
+}
+
+// One lane rasterizes a small triangle over its bounding box (Sec. 4.1): y outer, x inner,
+// incremental int32 edge values (see kSmallExtent for the range argument).
+template <bool STATS>
+__device__ __forceinline__ void raster_small(const SmallTri& s, uint64_t id, const ViewDesc& V, bool early_out,
+                                             StatAcc<STATS>& st)
+{
+    int32_t sdx[3], sdy[3], row[3], bias[3];
+    const int32_t Px0 = 256 * s.px0 + 128, Py0 = 256 * s.py0 + 128;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int a = k == 2 ? 0 : k + 1;
+        const int b = k == 0 ? 2 : k - 1;
+        const int32_t dx = s.X[b] - s.X[a];
+        const int32_t dy = s.Y[b] - s.Y[a];
+        bias[k] = top_left(dx, dy) ? 0 : -1;
+        row[k] = __mul24(dx, Py0 - s.Y[a]) - __mul24(dy, Px0 - s.X[a]) + bias[k];
+        sdx[k] = dx * 256;
+        sdy[k] = dy * 256;
+    }
+    const float area_f = (float)s.area;
+    for (int32_t py = s.py0; py <= s.py1; ++py) {
+        int32_t g0 = row[0], g1 = row[1], g2 = row[2];
+        for (int32_t px = s.px0; px <= s.px1; ++px) {
+            if ((g0 | g1 | g2) >= 0) {
+                const float depth = frag_depth((float)(g0 - bias[0]), (float)(g1 - bias[1]), (float)(g2 - bias[2]),
+                                               s.zI, area_f);
+                unsigned long long* p = V.vis + (size_t)py * (size_t)V.W + (size_t)px;
+                const unsigned long long key = make_key(depth, id);
+                st.add(kStFragments);
+                if (STATS) {
+                    if (!early_out || key < *p) st.add(kStAtomics);
+                }
+                write_fragment(p, key, early_out);
+            }
+            g0 -= sdy[0];
+            g1 -= sdy[1];
+            g2 -= sdy[2];
+        }
+        row[0] += sdx[0];
+        row[1] += sdx[1];
+        row[2] += sdx[2];
+    }
+}
+
+// One thread rasterizes any triangle (clipping, fan, int64 edges): the overflow fallback.
+__device__ inline void raster_any_thread(const Clip c[3], uint64_t id, const ViewDesc& V, bool early_out)
+{
+    Clip poly[8];
+    int n = 3;
+    if (outside_guard(c[0], V.near_plane) || outside_guard(c[1], V.near_plane) || outside_guard(c[2], V.near_plane)) {
+        n = clip_triangle(c, V.near_plane, poly);
+    } else {
+        poly[0] = c[0];
+        poly[1] = c[1];
+        poly[2] = c[2];
+    }
+    if (n < 3) return;
+    int32_t X[8], Y[8];
+    float zI[8];
+    for (int k = 0; k < n; ++k) snap_vertex(poly[k], V.hW, V.hH, X[k], Y[k], zI[k]);
+    for (int j = 1; j + 1 < n; ++j) {
+        const int32_t tx[3] = {X[0], X[j], X[j + 1]}, ty[3] = {Y[0], Y[j], Y[j + 1]};
+        const float tz[3] = {zI[0], zI[j], zI[j + 1]};
+        Tri64 t;
+        if (!setup_tri64(tx, ty, tz, V.W, V.H, t)) continue;
+        for (int32_t py = t.py0; py <= t.py1; ++py)
+            for (int32_t px = t.px0; px <= t.px1; ++px) raster_pixel64(t, px, py, id, V.vis, V.W, early_out);
+    }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Clear (also resets the queue counters of the frame)
+// ----------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) clear_kernel(RasterArgs a)
+{
+    if (blockIdx.x == 0 && threadIdx.x < kNumCounters) a.counters[threadIdx.x] = 0;
+    const uint32_t nv = a.hdr->n_views;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint32_t v = 0; v < nv; ++v) {
+        const ViewDesc V = a.views[v];
+        const uint64_t n = (uint64_t)V.W * (uint64_t)V.H;
+        if (((uintptr_t)V.vis & 15) == 0) {
+            ulonglong2* p = reinterpret_cast<ulonglong2*>(V.vis);
+            const uint64_t n2 = n >> 1;
+            for (uint64_t i = tid; i < n2; i += stride) p[i] = make_ulonglong2(~0ull, ~0ull);
+            if ((n & 1) && tid == 0) V.vis[n - 1] = ~0ull;
+        } else {
+            for (uint64_t i = tid; i < n; i += stride) V.vis[i] = ~0ull;
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Stage 1: one lane per triangle, looping over the draws (instances x views) of its work item
+// ----------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t find_segment(const Segment* segs, uint32_t n_segs, uint64_t b)
+{
+    uint32_t lo = 0, hi = n_segs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (segs[mid].batch_begin <= b) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+template <int BLOCK, int TPT, bool STATS>
+__global__ void __launch_bounds__(BLOCK) stage1_kernel(RasterArgs a)
+{
+    const uint64_t total = a.hdr->total_batches;
+    const uint32_t n_segs = a.hdr->n_segs;
+    const uint32_t dpi = a.hdr->draws_per_item;
+    const bool early_out = !(a.flags & kFlagNoEarlyOut);
+    const bool tiny_cull = !(a.flags & kFlagNoTinyCull);
+    StatAcc<STATS> st;
+    for (uint64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const Segment seg = a.segs[find_segment(a.segs, n_segs, b)];
+        const uint64_t j = b - seg.batch_begin;
+        const uint64_t tb = j / seg.n_groups;
+        const uint32_t g = (uint32_t)(j - tb * seg.n_groups);
+        const uint32_t d0 = seg.draw_begin + g * dpi;
+        const uint32_t d1 = min(seg.draw_begin + seg.draw_count, d0 + dpi);
+        const MeshDesc mesh = a.meshes[seg.mesh];
+#pragma unroll 1
+        for (int k = 0; k < TPT; ++k) {
+            const uint64_t t = tb * (uint64_t)(BLOCK * TPT) + (uint64_t)(k * BLOCK) + threadIdx.x;
+            bool valid = t < mesh.T;
+            float p[9];
+            if (valid) {
+                const uint32_t* ip = mesh.idx + 3 * t;
+                const uint32_t i0 = ip[0], i1 = ip[1], i2 = ip[2];
+                valid = i0 < mesh.V && i1 < mesh.V && i2 < mesh.V;
+                if (valid) {
+                    const float* q0 = mesh.pos + 3 * (size_t)i0;
+                    const float* q1 = mesh.pos + 3 * (size_t)i1;
+                    const float* q2 = mesh.pos + 3 * (size_t)i2;
+                    p[0] = q0[0]; p[1] = q0[1]; p[2] = q0[2];
+                    p[3] = q1[0]; p[4] = q1[1]; p[5] = q1[2];
+                    p[6] = q2[0]; p[7] = q2[1]; p[8] = q2[2];
+                }
+            }
+#pragma unroll 1
+            for (uint32_t d = d0; d < d1; ++d) {
+                const DrawDesc& D = a.draws[d];
+                const ViewDesc V = a.views[D.view];
+                int route = kRouteNone;
+                SmallTri s;
+                if (valid) {
+                    st.add(kStTriDraws);
+                    const Clip c[3] = {transform(D.A, p[0], p[1], p[2]), transform(D.A, p[3], p[4], p[5]),
+                                       transform(D.A, p[6], p[7], p[8])};
+                    route = classify<STATS>(c, V, a.small_px, tiny_cull, s, st);
+                }
+                const unsigned long long slot = wave_reserve(route == kRouteForward, a.counters + kCntQ2);
+                if (route == kRouteForward) {
+                    st.add(kStQ2);
+                    if (slot < a.q2_cap) {
+                        Q2Entry e;
+                        e.draw = d;
+                        e.tri = (uint32_t)t;
+                        a.q2[slot] = e;
+                    } else {
+                        st.add(kStQ2Overflow);
+                    }
+                }
+                if (route == kRouteSmall) {
+                    st.add(kStS1Raster);
+                    raster_small<STATS>(s, D.id_base + t, V, early_out, st);
+                }
+            }
+        }
+    }
+    st.flush(a.stats);
+}
+
+// Stage-1 overflow pass: when more triangles were forwarded than Q2 holds, every forwarded
+// triangle is rasterized here by one thread (those that did fit are drawn twice; the minimum is
+// idempotent).  Exits at once when nothing overflowed.
+__global__ void __launch_bounds__(256) stage1_overflow_kernel(RasterArgs a)
+{
+    if (a.counters[kCntQ2] <= a.q2_cap) return;
+    const uint64_t total = a.hdr->total_batches;
+    const uint32_t n_segs = a.hdr->n_segs;
+    const uint32_t dpi = a.hdr->draws_per_item;
+    const uint32_t bt = a.hdr->batch_tris;
+    const bool early_out = !(a.flags & kFlagNoEarlyOut);
+    const bool tiny_cull = !(a.flags & kFlagNoTinyCull);
+    StatAcc<false> st;
+    for (uint64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const Segment seg = a.segs[find_segment(a.segs, n_segs, b)];
+        const uint64_t j = b - seg.batch_begin;
+        const uint64_t tb = j / seg.n_groups;
+        const uint32_t g = (uint32_t)(j - tb * seg.n_groups);
+        const uint32_t d0 = seg.draw_begin + g * dpi;
+        const uint32_t d1 = min(seg.draw_begin + seg.draw_count, d0 + dpi);
+        const MeshDesc mesh = a.meshes[seg.mesh];
+        for (uint32_t tt = threadIdx.x; tt < bt; tt += blockDim.x) {
+            const uint64_t t = tb * bt + tt;
+            if (t >= mesh.T) break;
+            const uint32_t i0 = mesh.idx[3 * t], i1 = mesh.idx[3 * t + 1], i2 = mesh.idx[3 * t + 2];
+            if (i0 >= mesh.V || i1 >= mesh.V || i2 >= mesh.V) continue;
+            for (uint32_t d = d0; d < d1; ++d) {
+                const DrawDesc& D = a.draws[d];
+                const ViewDesc V = a.views[D.view];
+                const Clip c[3] = {transform(D.A, mesh.pos[3 * (size_t)i0], mesh.pos[3 * (size_t)i0 + 1], mesh.pos[3 * (size_t)i0 + 2]),
+                                   transform(D.A, mesh.pos[3 * (size_t)i1], mesh.pos[3 * (size_t)i1 + 1], mesh.pos[3 * (size_t)i1 + 2]),
+                                   transform(D.A, mesh.pos[3 * (size_t)i2], mesh.pos[3 * (size_t)i2 + 1], mesh.pos[3 * (size_t)i2 + 2])};
+                SmallTri s;
+                if (classify<false>(c, V, a.small_px, tiny_cull, s, st) == kRouteForward)
+                    raster_any_thread(c, D.id_base + t, V, early_out);
+            }
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Stage 2: one wavefront per forwarded triangle (Sec. 4.2)
+// ----------------------------------------------------------------------------------------------
+template <bool STATS>
+__global__ void __launch_bounds__(256) stage2_kernel(RasterArgs a)
+{
+    const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
+    const unsigned long long n = min(a.counters[kCntQ2], (unsigned long long)a.q2_cap);
+    const bool early_out = !(a.flags & kFlagNoEarlyOut);
+    StatAcc<STATS> st;
+    for (unsigned long long e = wave; e < n; e += nwaves) {
+        const Q2Entry q = a.q2[e];
+        const uint32_t d = __builtin_amdgcn_readfirstlane(q.draw);
+        const uint32_t t = __builtin_amdgcn_readfirstlane(q.tri);
+        const DrawDesc& D = a.draws[d];
+        const ViewDesc V = a.views[D.view];
+        const MeshDesc M = a.meshes[D.mesh];
+        const uint64_t id = D.id_base + t;
+        Clip c[3];
+        for (int k = 0; k < 3; ++k) {
+            const uint32_t vi = M.idx[3 * (uint64_t)t + k];
+            c[k] = transform(D.A, M.pos[3 * (size_t)vi], M.pos[3 * (size_t)vi + 1], M.pos[3 * (size_t)vi + 2]);
+        }
+        Clip poly[8];
+        int np = 3;
+        if (outside_guard(c[0], V.near_plane) || outside_guard(c[1], V.near_plane) ||
+            outside_guard(c[2], V.near_plane)) {
+            np = clip_triangle(c, V.near_plane, poly);
+        } else {
+            poly[0] = c[0];
+            poly[1] = c[1];
+            poly[2] = c[2];
+        }
+        int32_t X[8], Y[8];
+        float zI[8];
+        for (int k = 0; k < np; ++k) snap_vertex(poly[k], V.hW, V.hH, X[k], Y[k], zI[k]);
+        for (int j = 1; j + 1 < np; ++j) {
+            const int32_t tx[3] = {X[0], X[j], X[j + 1]}, ty[3] = {Y[0], Y[j], Y[j + 1]};
+            const float tz[3] = {zI[0], zI[j], zI[j + 1]};
+            Tri64 tri;
+            if (!setup_tri64(tx, ty, tz, V.W, V.H, tri)) continue;
+            const uint32_t bw = (uint32_t)(tri.px1 - tri.px0 + 1);
+            const uint64_t cnt = (uint64_t)bw * (uint64_t)(tri.py1 - tri.py0 + 1);
+            bool in_place = cnt <= a.medium_px;
+            if (!in_place) {
+                const uint32_t tx0 = tri.px0 / kTileSize, tx1 = tri.px1 / kTileSize;
+                const uint32_t ty0 = tri.py0 / kTileSize, ty1 = tri.py1 / kTileSize;
+                const uint32_t ntx = tx1 - tx0 + 1;
+                const uint64_t ntiles = (uint64_t)ntx * (uint64_t)(ty1 - ty0 + 1);
+                unsigned long long rec = 0, qbase = 0;
+                if (lane == 0) {
+                    rec = atomicAdd(a.counters + kCntLarge, 1ull);
+                    qbase = atomicAdd(a.counters + kCntQ3, (unsigned long long)ntiles);
+                }
+                rec = __shfl(rec, 0);
+                qbase = __shfl(qbase, 0);
+                const bool ok = rec < a.large_cap && qbase + ntiles <= a.q3_cap;
+                if (ok) {
+                    if (lane == 0) {
+                        LargeTri r;
+                        for (int k = 0; k < 3; ++k) {
+                            r.X[k] = tx[k];
+                            r.Y[k] = ty[k];
+                            r.zI[k] = tz[k];
+                        }
+                        r.view = D.view;
+                        r.id = id;
+                        a.large[rec] = r;
+                    }
+                    for (uint64_t i = lane; i < ntiles; i += 64) {
+                        Q3Entry qe;
+                        qe.rec = (uint32_t)rec;
+                        qe.tx = (uint16_t)(tx0 + (uint32_t)(i % ntx));
+                        qe.ty = (uint16_t)(ty0 + (uint32_t)(i / ntx));
+                        a.q3[qbase + i] = qe;
+                    }
+                    if (lane == 0) st.add(kStQ3, (uint32_t)ntiles);
+                } else {
+                    // the reserved range may start inside the queue: mark those slots empty
+                    for (uint64_t i = lane; i < ntiles && qbase + i < a.q3_cap; i += 64) {
+                        Q3Entry qe;
+                        qe.rec = kNullRecord;
+                        qe.tx = 0;
+                        qe.ty = 0;
+                        a.q3[qbase + i] = qe;
+                    }
+                    if (lane == 0) st.add(kStQ3Overflow);
+                    in_place = true;
+                }
+            }
+            if (in_place) {
+                if (lane == 0) st.add(kStS2Raster);
+                for (uint64_t i = lane; i < cnt; i += 64) {
+                    const int32_t px = tri.px0 + (int32_t)(i % bw);
+                    const int32_t py = tri.py0 + (int32_t)(i / bw);
+                    if (raster_pixel64(tri, px, py, id, V.vis, V.W, early_out)) st.add(kStFragments);
+                }
+            }
+        }
+    }
+    st.flush(a.stats);
+}
+
+// ----------------------------------------------------------------------------------------------
+// Stage 3: one workgroup of 256 lanes per 64x64 tile part (Sec. 4.3); lane l covers column l % 64
+// and every fourth row from l / 64.
+// ----------------------------------------------------------------------------------------------
+template <bool STATS>
+__global__ void __launch_bounds__(256) stage3_kernel(RasterArgs a)
+{
+    const unsigned long long n = min(a.counters[kCntQ3], (unsigned long long)a.q3_cap);
+    const bool early_out = !(a.flags & kFlagNoEarlyOut);
+    const int32_t col = threadIdx.x & 63;
+    const int32_t row0 = threadIdx.x >> 6;
+    StatAcc<STATS> st;
+    for (unsigned long long e = blockIdx.x; e < n; e += gridDim.x) {
+        const Q3Entry q = a.q3[e];
+        if (q.rec == kNullRecord) continue;
+        const LargeTri r = a.large[q.rec];
+        const ViewDesc V = a.views[r.view];
+        Tri64 tri;
+        if (!setup_tri64(r.X, r.Y, r.zI, V.W, V.H, tri)) continue;
+        const int32_t px = (int32_t)q.tx * kTileSize + col;
+        const int32_t y0 = max(tri.py0, (int32_t)q.ty * kTileSize);
+        const int32_t y1 = min(tri.py1, (int32_t)q.ty * kTileSize + kTileSize - 1);
+        if (px < tri.px0 || px > tri.px1) continue;
+        int32_t py = (int32_t)q.ty * kTileSize + row0;
+        while (py < y0) py += 4;
+        for (; py <= y1; py += 4)
+            if (raster_pixel64(tri, px, py, r.id, V.vis, V.W, early_out)) st.add(kStFragments);
+    }
+    st.flush(a.stats);
+}
+
+// ----------------------------------------------------------------------------------------------
+// Launch wrappers
+// ----------------------------------------------------------------------------------------------
+hipError_t launch_clear(const RasterArgs& a, uint32_t grid, hipStream_t s)
+{
+    clear_kernel<<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int BLOCK, int TPT>
+static hipError_t stage1_dispatch(const RasterArgs& a, bool stats, uint32_t grid, hipStream_t s)
+{
+    if (stats) stage1_kernel<BLOCK, TPT, true><<<grid, BLOCK, 0, s>>>(a);
+    else stage1_kernel<BLOCK, TPT, false><<<grid, BLOCK, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+template <int BLOCK>
+static hipError_t stage1_tpt(const RasterArgs& a, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s)
+{
+    switch (tpt) {
+    case 1: return stage1_dispatch<BLOCK, 1>(a, stats, grid, s);
+    case 2: return stage1_dispatch<BLOCK, 2>(a, stats, grid, s);
+    case 4: return stage1_dispatch<BLOCK, 4>(a, stats, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s)
+{
+    switch (block) {
+    case 64: return stage1_tpt<64>(a, tpt, stats, grid, s);
+    case 128: return stage1_tpt<128>(a, tpt, stats, grid, s);
+    case 256: return stage1_tpt<256>(a, tpt, stats, grid, s);
+    case 512: return stage1_tpt<512>(a, tpt, stats, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stage1_overflow(const RasterArgs& a, uint32_t grid, hipStream_t s)
+{
+    stage1_overflow_kernel<<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage2(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s)
+{
+    if (stats) stage2_kernel<true><<<grid, 256, 0, s>>>(a);
+    else stage2_kernel<false><<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage3(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s)
+{
+    if (stats) stage3_kernel<true><<<grid, 256, 0, s>>>(a);
+    else stage3_kernel<false><<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace curast

@@ -1,0 +1,253 @@
+// Resolve kernels for gfx950 (Sec. 4.4): one lane per pixel decodes the 28-bit depth / 36-bit
+// global triangle ID, finds the (mesh, instance) by binary search over the int64 exclusive
+// prefix of triangle counts, reloads and re-projects the triangle, and interpolates its vertex
+// attributes perspective-correctly at the pixel centre.  The paper shades in world space with a
+// ray-plane intersection; the equivalent screen-space form used here is
+//   b_k = q_k / (q0 + q1 + q2), q_k = lambda_k / w_k,
+// lambda_k the 2-D cross products of the pixel-relative projected vertices, which stays valid for
+// vertices behind the camera (the resolve uses the unclipped triangle).  The backward kernel
+// differentiates that expression with visibility held fixed.
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace curast {
+
+struct Interp {
+    float d[3][2];   // pixel-relative window positions
+    float zI[3];
+    float lam[3];
+    float s;
+    float b[3];
+};
+
+// fp32 interpolation weights in a fixed operation order (no contraction).
+__device__ __forceinline__ void interp_weights(const float sx[3], const float sy[3], const float w[3], int32_t px,
+                                               int32_t py, Interp& r)
+{
+    const float cx = (float)px + 0.5f, cy = (float)py + 0.5f;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        r.d[k][0] = sx[k] - cx;
+        r.d[k][1] = sy[k] - cy;
+        r.zI[k] = 1.0f / w[k];
+    }
+    r.lam[0] = r.d[1][0] * r.d[2][1] - r.d[1][1] * r.d[2][0];
+    r.lam[1] = r.d[2][0] * r.d[0][1] - r.d[2][1] * r.d[0][0];
+    r.lam[2] = r.d[0][0] * r.d[1][1] - r.d[0][1] * r.d[1][0];
+    const float q0 = r.lam[0] * r.zI[0], q1 = r.lam[1] * r.zI[1], q2 = r.lam[2] * r.zI[2];
+    r.s = (q0 + q1) + q2;
+    r.b[0] = q0 / r.s;
+    r.b[1] = q1 / r.s;
+    r.b[2] = q2 / r.s;
+}
+
+__device__ __forceinline__ void write_interp(const Interp& r, const float* a0, const float* a1, const float* a2,
+                                             uint32_t C, float* o)
+{
+    for (uint32_t c = 0; c < C; ++c) o[c] = (r.b[0] * a0[c] + r.b[1] * a1[c]) + r.b[2] * a2[c];
+}
+
+__device__ __forceinline__ void write_zero(uint32_t C, float* o)
+{
+    for (uint32_t c = 0; c < C; ++c) o[c] = 0.0f;
+}
+
+// ----------------------------------------------------------------------------------------------
+// Window positions of one mesh instance: pos_ss[v] = (sx, sy, w) before snapping
+// ----------------------------------------------------------------------------------------------
+struct ProjectArgs {
+    const float* pos;
+    uint32_t V;
+    float A[12];
+    float hW, hH;
+    float* out;
+};
+
+__global__ void __launch_bounds__(256) project_kernel(ProjectArgs a)
+{
+    const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= a.V) return;
+    const Clip c = transform(a.A, a.pos[3 * v], a.pos[3 * v + 1], a.pos[3 * v + 2]);
+    const float zI = 1.0f / c.w;
+    a.out[3 * v + 0] = __builtin_fmaf(c.x * zI, a.hW, a.hW);
+    a.out[3 * v + 1] = __builtin_fmaf(c.y * zI, a.hH, a.hH);
+    a.out[3 * v + 2] = c.w;
+}
+
+// ----------------------------------------------------------------------------------------------
+// Resolve of a multi-mesh, multi-instance visibility buffer
+// ----------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) resolve_kernel(ResolveArgs a)
+{
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t npix = (uint64_t)a.W * (uint64_t)a.H;
+    if (p >= npix) return;
+    float* o = a.out + p * a.C;
+    const unsigned long long key = a.vis[p];
+    const uint64_t id = key & kIdMask;
+    if (key == kEmptyKey || id >= a.bases[a.n_pairs]) {
+        write_zero(a.C, o);
+        return;
+    }
+    uint32_t lo = 0, hi = a.n_pairs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (a.bases[mid] <= id) lo = mid;
+        else hi = mid;
+    }
+    const DrawDesc& D = a.pairs[lo];
+    const MeshDesc M = a.meshes[D.mesh];
+    const uint64_t t = id - a.bases[lo];
+    const uint32_t vi[3] = {M.idx[3 * t], M.idx[3 * t + 1], M.idx[3 * t + 2]};
+    if (vi[0] >= M.V || vi[1] >= M.V || vi[2] >= M.V) {
+        write_zero(a.C, o);
+        return;
+    }
+    float sx[3], sy[3], w[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const float* q = M.pos + 3 * (size_t)vi[k];
+        const Clip c = transform(D.A, q[0], q[1], q[2]);
+        const float zI = 1.0f / c.w;
+        sx[k] = __builtin_fmaf(c.x * zI, a.hW, a.hW);
+        sy[k] = __builtin_fmaf(c.y * zI, a.hH, a.hH);
+        w[k] = c.w;
+    }
+    const int32_t px = (int32_t)(p % (uint64_t)a.W), py = (int32_t)(p / (uint64_t)a.W);
+    Interp r;
+    interp_weights(sx, sy, w, px, py, r);
+    const float* at = a.attrs[D.mesh];
+    write_interp(r, at + (size_t)vi[0] * a.C, at + (size_t)vi[1] * a.C, at + (size_t)vi[2] * a.C, a.C, o);
+}
+
+// ----------------------------------------------------------------------------------------------
+// Screen-space (differentiable) resolve of one mesh and its backward pass
+// ----------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool screen_tri(const ScreenArgs& a, uint64_t p, uint32_t vi[3])
+{
+    const unsigned long long key = a.vis[p];
+    if (key == kEmptyKey) return false;
+    const uint64_t id = key & kIdMask;
+    if (id < a.id_base || id - a.id_base >= a.T) return false;
+    const uint64_t t = id - a.id_base;
+    vi[0] = a.idx[3 * t];
+    vi[1] = a.idx[3 * t + 1];
+    vi[2] = a.idx[3 * t + 2];
+    return vi[0] < a.V && vi[1] < a.V && vi[2] < a.V;
+}
+
+__global__ void __launch_bounds__(256) resolve_screen_kernel(ScreenArgs a)
+{
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (uint64_t)a.W * (uint64_t)a.H) return;
+    float* o = a.out + p * a.C;
+    uint32_t vi[3];
+    if (!screen_tri(a, p, vi)) {
+        write_zero(a.C, o);
+        return;
+    }
+    float sx[3], sy[3], w[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        sx[k] = a.pos_ss[3 * (size_t)vi[k]];
+        sy[k] = a.pos_ss[3 * (size_t)vi[k] + 1];
+        w[k] = a.pos_ss[3 * (size_t)vi[k] + 2];
+    }
+    Interp r;
+    interp_weights(sx, sy, w, (int32_t)(p % (uint64_t)a.W), (int32_t)(p / (uint64_t)a.W), r);
+    write_interp(r, a.attrs + (size_t)vi[0] * a.C, a.attrs + (size_t)vi[1] * a.C, a.attrs + (size_t)vi[2] * a.C, a.C, o);
+}
+
+// dL/da_k = g b_k;  G_k = g . a_k;  dL/dq_j = (G_j - sum_k G_k b_k) / s;
+// dL/dlambda_j = dL/dq_j zI_j;  dL/dw_j = -(dL/dq_j lambda_j) zI_j^2;
+// lambda_0 = d1 x d2, lambda_1 = d2 x d0, lambda_2 = d0 x d1 with d_k = s_k - pixel centre.
+__global__ void __launch_bounds__(256) resolve_backward_kernel(ScreenArgs a)
+{
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (uint64_t)a.W * (uint64_t)a.H) return;
+    uint32_t vi[3];
+    if (!screen_tri(a, p, vi)) return;
+    float sx[3], sy[3], w[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        sx[k] = a.pos_ss[3 * (size_t)vi[k]];
+        sy[k] = a.pos_ss[3 * (size_t)vi[k] + 1];
+        w[k] = a.pos_ss[3 * (size_t)vi[k] + 2];
+    }
+    Interp r;
+    interp_weights(sx, sy, w, (int32_t)(p % (uint64_t)a.W), (int32_t)(p / (uint64_t)a.W), r);
+    const float* g = a.grad_out + p * a.C;
+    float G[3] = {0.0f, 0.0f, 0.0f};
+    for (uint32_t c = 0; c < a.C; ++c) {
+        const float gc = g[c];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float ac = a.attrs[(size_t)vi[k] * a.C + c];
+            G[k] = G[k] + gc * ac;
+            unsafeAtomicAdd(a.grad_attr + (size_t)vi[k] * a.C + c, gc * r.b[k]);
+        }
+    }
+    if (!a.grad_pos) return;
+    const float Gb = (G[0] * r.b[0] + G[1] * r.b[1]) + G[2] * r.b[2];
+    float L[3], dw[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const float Q = (G[j] - Gb) / r.s;
+        L[j] = Q * r.zI[j];
+        dw[j] = -((Q * r.lam[j]) * r.zI[j]) * r.zI[j];
+    }
+    const float(*d)[2] = r.d;
+    float gx[3], gy[3];
+    gx[0] = L[2] * d[1][1] - L[1] * d[2][1];
+    gy[0] = L[1] * d[2][0] - L[2] * d[1][0];
+    gx[1] = L[0] * d[2][1] - L[2] * d[0][1];
+    gy[1] = L[2] * d[0][0] - L[0] * d[2][0];
+    gx[2] = L[1] * d[0][1] - L[0] * d[1][1];
+    gy[2] = L[0] * d[1][0] - L[1] * d[0][0];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        unsafeAtomicAdd(a.grad_pos + 3 * (size_t)vi[k] + 0, gx[k]);
+        unsafeAtomicAdd(a.grad_pos + 3 * (size_t)vi[k] + 1, gy[k]);
+        unsafeAtomicAdd(a.grad_pos + 3 * (size_t)vi[k] + 2, dw[k]);
+    }
+}
+
+// ----------------------------------------------------------------------------------------------
+// Launch wrappers
+// ----------------------------------------------------------------------------------------------
+static uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + 255) / 256); }
+
+hipError_t launch_project(const float* pos, uint32_t V, const float A[12], float hW, float hH, float* out, hipStream_t s)
+{
+    ProjectArgs a;
+    a.pos = pos;
+    a.V = V;
+    for (int i = 0; i < 12; ++i) a.A[i] = A[i];
+    a.hW = hW;
+    a.hH = hH;
+    a.out = out;
+    if (V == 0) return hipSuccess;
+    project_kernel<<<blocks_for(V), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s)
+{
+    resolve_kernel<<<blocks_for((uint64_t)a.W * (uint64_t)a.H), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve_screen(const ScreenArgs& a, hipStream_t s)
+{
+    resolve_screen_kernel<<<blocks_for((uint64_t)a.W * (uint64_t)a.H), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve_backward(const ScreenArgs& a, hipStream_t s)
+{
+    resolve_backward_kernel<<<blocks_for((uint64_t)a.W * (uint64_t)a.H), 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+}  // namespace curast

@@ -1,0 +1,957 @@
+// Host runtime of the rasterizer and its C ABI (include/curast.h).
+//
+// Per frame the host (Sec. 4: "before launching the rasterization stages") computes the draw
+// matrix of every (mesh, instance, view), the int64 exclusive prefix of triangle counts that
+// gives global triangle IDs, culls whole (mesh, instance, view) draws by their bounding sphere,
+// splits the surviving work into stage-1 work items, and uploads these descriptors with one
+// asynchronous copy from pinned memory.  Everything after that (clear, stages 1-3, resolve) is
+// device-side and reads counts from device memory, so a batched frame is captured once into a
+// hipGraph and replayed with new descriptor contents.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/curast.h"
+#include "common.h"
+
+namespace curast {
+hipError_t launch_clear(const RasterArgs& a, uint32_t grid, hipStream_t s);
+hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s);
+hipError_t launch_stage1_overflow(const RasterArgs& a, uint32_t grid, hipStream_t s);
+hipError_t launch_stage2(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
+hipError_t launch_stage3(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
+hipError_t launch_project(const float* pos, uint32_t V, const float A[12], float hW, float hH, float* out, hipStream_t s);
+hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s);
+hipError_t launch_resolve_screen(const ScreenArgs& a, hipStream_t s);
+hipError_t launch_resolve_backward(const ScreenArgs& a, hipStream_t s);
+}  // namespace curast
+
+using namespace curast;
+
+namespace {
+
+constexpr uint64_t kMaxIds = uint64_t(1) << 36;
+
+// Stage timing slots (CURAST_FLAG_TIMING).
+enum Slot : int { kTClear = 0, kTS1, kTS1Overflow, kTS2, kTS3, kTResolve, kTResolveBwd, kTFrame, kNumSlots };
+
+struct TimedFrame {
+    hipEvent_t ev[kNumSlots + 1];
+    int used[kNumSlots];
+};
+
+// Pinned staging buffer + device buffer + event guarding reuse of the host side.
+struct Staging {
+    void* host = nullptr;
+    void* dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+    bool pending = false;
+};
+
+struct GraphEntry {
+    uint64_t key[8];
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct curast_ctx {
+    int device = 0;
+    int cus = 256;
+    curast_options user{};
+    curast_options opt{};   // user options with defaults filled in
+    std::string err;
+    Staging raster_stage, resolve_stage;
+    Q2Entry* q2 = nullptr;
+    LargeTri* large = nullptr;
+    Q3Entry* q3 = nullptr;
+    uint32_t q2_alloc = 0, large_alloc = 0, q3_alloc = 0;
+    unsigned long long* counters = nullptr;
+    unsigned long long* stats = nullptr;
+    hipStream_t capture_stream = nullptr;
+    std::vector<GraphEntry> graphs;
+    std::vector<TimedFrame> timed;
+    double stage_ms[kNumSlots] = {0};
+    uint64_t timed_frames = 0;
+    uint64_t draws_culled = 0;
+};
+
+namespace {
+
+int fail(curast_ctx* ctx, int code, const std::string& msg)
+{
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int hip_fail(curast_ctx* ctx, hipError_t e, const char* what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (ctx) ctx->err = m;
+    return CURAST_E_HIP;
+}
+
+#define HIP_TRY(ctx, expr)                                  \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, #expr); \
+    } while (0)
+
+int validate_options(const curast_options& o, std::string& msg)
+{
+    auto bad = [&](const char* m) { msg = m; return CURAST_E_INVALID; };
+    if (o.s1_block && o.s1_block != 64 && o.s1_block != 128 && o.s1_block != 256 && o.s1_block != 512)
+        return bad("s1_block must be 64, 128, 256 or 512");
+    if (o.s1_tris_per_thread && o.s1_tris_per_thread != 1 && o.s1_tris_per_thread != 2 && o.s1_tris_per_thread != 4)
+        return bad("s1_tris_per_thread must be 1, 2 or 4");
+    if (o.small_px > 65536) return bad("small_px must be <= 65536");
+    if (o.s1_draws_per_item > 65536) return bad("s1_draws_per_item must be <= 65536");
+    if (o.q2_capacity > (1u << 30) || o.q3_capacity > (1u << 30) || o.large_capacity > (1u << 28))
+        return bad("queue capacity too large");
+    return CURAST_OK;
+}
+
+curast_options resolve_defaults(const curast_options& u, int cus)
+{
+    curast_options o = u;
+    if (!o.small_px) o.small_px = 128;
+    if (!o.medium_px) o.medium_px = 4096;
+    if (!o.s1_block) o.s1_block = 256;
+    if (!o.s1_tris_per_thread) o.s1_tris_per_thread = 1;
+    if (!o.s1_draws_per_item) o.s1_draws_per_item = 64;
+    if (!o.s2_waves) o.s2_waves = (uint32_t)cus * 4;
+    if (!o.s3_blocks) o.s3_blocks = (uint32_t)cus * 2;
+    if (!o.q2_capacity) o.q2_capacity = 1u << 20;
+    if (!o.q3_capacity) o.q3_capacity = 1u << 20;
+    if (!o.large_capacity) o.large_capacity = 1u << 18;
+    return o;
+}
+
+void drop_graphs(curast_ctx* ctx)
+{
+    for (auto& g : ctx->graphs) {
+        if (g.exec) hipGraphExecDestroy(g.exec);
+        if (g.graph) hipGraphDestroy(g.graph);
+    }
+    ctx->graphs.clear();
+}
+
+int ensure_staging(curast_ctx* ctx, Staging& st, size_t bytes)
+{
+    if (st.pending) {
+        HIP_TRY(ctx, hipEventSynchronize(st.ev));
+        st.pending = false;
+    }
+    if (bytes <= st.cap) return CURAST_OK;
+    size_t cap = std::max<size_t>(bytes, std::max<size_t>(st.cap * 2, 64 * 1024));
+    if (st.host) hipHostFree(st.host);
+    if (st.dev) hipFree(st.dev);
+    st.host = nullptr;
+    st.dev = nullptr;
+    st.cap = 0;
+    if (hipHostMalloc(&st.host, cap, hipHostMallocDefault) != hipSuccess) return fail(ctx, CURAST_E_OOM, "pinned staging allocation failed");
+    if (hipMalloc(&st.dev, cap) != hipSuccess) return fail(ctx, CURAST_E_OOM, "descriptor allocation failed");
+    st.cap = cap;
+    drop_graphs(ctx);   // descriptor buffers moved: captured graphs refer to the old ones
+    return CURAST_OK;
+}
+
+int ensure_queues(curast_ctx* ctx)
+{
+    const bool zero = ctx->opt.flags & kFlagZeroQueues;
+    const uint32_t q2 = zero ? 1 : ctx->opt.q2_capacity;
+    const uint32_t q3 = zero ? 1 : ctx->opt.q3_capacity;
+    const uint32_t lg = zero ? 1 : ctx->opt.large_capacity;
+    if (q2 > ctx->q2_alloc) {
+        if (ctx->q2) hipFree(ctx->q2);
+        ctx->q2 = nullptr;
+        ctx->q2_alloc = 0;
+        if (hipMalloc(&ctx->q2, sizeof(Q2Entry) * (size_t)q2) != hipSuccess) return fail(ctx, CURAST_E_OOM, "Q2 allocation failed");
+        ctx->q2_alloc = q2;
+        drop_graphs(ctx);
+    }
+    if (q3 > ctx->q3_alloc) {
+        if (ctx->q3) hipFree(ctx->q3);
+        ctx->q3 = nullptr;
+        ctx->q3_alloc = 0;
+        if (hipMalloc(&ctx->q3, sizeof(Q3Entry) * (size_t)q3) != hipSuccess) return fail(ctx, CURAST_E_OOM, "Q3 allocation failed");
+        ctx->q3_alloc = q3;
+        drop_graphs(ctx);
+    }
+    if (lg > ctx->large_alloc) {
+        if (ctx->large) hipFree(ctx->large);
+        ctx->large = nullptr;
+        ctx->large_alloc = 0;
+        if (hipMalloc(&ctx->large, sizeof(LargeTri) * (size_t)lg) != hipSuccess) return fail(ctx, CURAST_E_OOM, "large-triangle allocation failed");
+        ctx->large_alloc = lg;
+        drop_graphs(ctx);
+    }
+    return CURAST_OK;
+}
+
+// Draw matrix: rows x, y, w of VP times the object-to-world matrix X (identity when null), in the
+// fixed binary32 operation order of the result definition.
+void draw_matrix(const float vp[16], const float* X, float A[12])
+{
+    static const float I[12] = {1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0};
+    const float* x = X ? X : I;
+    static const int rows[3] = {0, 1, 3};
+    for (int r = 0; r < 3; ++r) {
+        const float* v = vp + 4 * rows[r];
+        for (int c = 0; c < 4; ++c) {
+            float t = v[0] * x[c];
+            t = t + v[1] * x[4 + c];
+            t = t + v[2] * x[8 + c];
+            if (c == 3) t = t + v[3];
+            A[4 * r + c] = t;
+        }
+    }
+}
+
+// Conservative bounding-sphere test against the view frustum (x = +-w, y = +-w, w = near) in
+// double precision with a relative safety margin: true only when every point of the sphere lies
+// strictly outside one plane, so no pixel centre can be covered by any triangle inside it.
+bool sphere_outside(const float A[12], const float bs[4], float near_plane)
+{
+    if (!(bs[3] > 0.0f)) return false;
+    double rx[4], ry[4], rw[4];
+    for (int c = 0; c < 4; ++c) {
+        rx[c] = A[c];
+        ry[c] = A[4 + c];
+        rw[c] = A[8 + c];
+    }
+    const double cx = bs[0], cy = bs[1], cz = bs[2], r = bs[3];
+    auto test = [&](const double* pl) {
+        const double v = pl[0] * cx + pl[1] * cy + pl[2] * cz + pl[3];
+        const double g = std::sqrt(pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2]);
+        const double mag = std::fabs(pl[0] * cx) + std::fabs(pl[1] * cy) + std::fabs(pl[2] * cz) + std::fabs(pl[3]) + r * g;
+        return v + r * g + 1e-4 * mag < 0.0;
+    };
+    double pl[4];
+    for (int c = 0; c < 4; ++c) pl[c] = rw[c] + rx[c];
+    if (test(pl)) return true;
+    for (int c = 0; c < 4; ++c) pl[c] = rw[c] - rx[c];
+    if (test(pl)) return true;
+    for (int c = 0; c < 4; ++c) pl[c] = rw[c] + ry[c];
+    if (test(pl)) return true;
+    for (int c = 0; c < 4; ++c) pl[c] = rw[c] - ry[c];
+    if (test(pl)) return true;
+    for (int c = 0; c < 4; ++c) pl[c] = rw[c] - (c == 3 ? (double)near_plane : 0.0);
+    return test(pl);
+}
+
+int check_view(curast_ctx* ctx, const curast_view& v, bool need_vis = true)
+{
+    if (v.width < 1 || v.height < 1 || v.width > kMaxDim || v.height > kMaxDim)
+        return fail(ctx, CURAST_E_INVALID, "view width/height must lie in [1, 16384]");
+    if (!(v.near_plane > 0.0f) || !std::isfinite(v.near_plane) || v.near_plane < 1e-30f)
+        return fail(ctx, CURAST_E_INVALID, "near plane must be finite and > 0");
+    for (int i = 0; i < 16; ++i)
+        if (!std::isfinite(v.view_proj[i])) return fail(ctx, CURAST_E_INVALID, "view_proj must be finite");
+    if (need_vis && !v.visbuffer) return fail(ctx, CURAST_E_INVALID, "visbuffer is NULL");
+    return CURAST_OK;
+}
+
+int check_mesh(curast_ctx* ctx, const curast_mesh& m)
+{
+    if (m.num_triangles > 0xFFFFFFFFull) return fail(ctx, CURAST_E_INVALID, "a mesh may hold at most 2^32-1 triangles");
+    if (m.num_triangles && (!m.vertices || !m.indices || m.num_vertices == 0))
+        return fail(ctx, CURAST_E_INVALID, "mesh with triangles needs vertices and indices");
+    if (m.instances && m.num_instances == 0) return fail(ctx, CURAST_E_INVALID, "instances given with num_instances == 0");
+    if (m.instances)
+        for (uint64_t i = 0; i < 12ull * m.num_instances; ++i)
+            if (!std::isfinite(m.instances[i])) return fail(ctx, CURAST_E_INVALID, "instance matrices must be finite");
+    return CURAST_OK;
+}
+
+uint32_t n_inst(const curast_mesh& m) { return m.instances ? m.num_instances : 1u; }
+
+struct Plan {
+    FrameHeader hdr{};
+    std::vector<ViewDesc> views;
+    std::vector<MeshDesc> meshes;
+    std::vector<Segment> segs;
+    std::vector<DrawDesc> draws;
+    uint64_t tri_draws = 0;
+    uint64_t draws_culled = 0;
+    uint64_t total_pixels = 0;
+    uint64_t max_batches = 0;        // without any culling (graph grid bound)
+    size_t max_draws = 0;            // without any culling
+    size_t off_views = 0, off_meshes = 0, off_segs = 0, off_draws = 0, bytes = 0, max_bytes = 0;
+};
+
+int build_plan(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* views, uint32_t n_views,
+               Plan& P)
+{
+    if (M && !meshes) return fail(ctx, CURAST_E_INVALID, "meshes is NULL");
+    if (!views || n_views == 0) return fail(ctx, CURAST_E_INVALID, "no view");
+    for (uint32_t v = 0; v < n_views; ++v) {
+        int rc = check_view(ctx, views[v]);
+        if (rc) return rc;
+        for (uint32_t u = 0; u < v; ++u)
+            if (views[u].visbuffer == views[v].visbuffer)
+                return fail(ctx, CURAST_E_INVALID, "views must have distinct visibility buffers");
+    }
+    uint64_t total_ids = 0;
+    for (uint32_t m = 0; m < M; ++m) {
+        int rc = check_mesh(ctx, meshes[m]);
+        if (rc) return rc;
+        total_ids += meshes[m].num_triangles * (uint64_t)n_inst(meshes[m]);
+        if (total_ids > kMaxIds) return fail(ctx, CURAST_E_ID_RANGE, "more than 2^36 triangle instances");
+    }
+    const curast_options& o = ctx->opt;
+    const bool cull = !(o.flags & kFlagNoMeshCull);
+    const uint32_t bt = o.s1_block * o.s1_tris_per_thread;
+    const uint32_t dpi = o.s1_draws_per_item;
+    P.views.resize(n_views);
+    for (uint32_t v = 0; v < n_views; ++v) {
+        ViewDesc& d = P.views[v];
+        d.vis = reinterpret_cast<unsigned long long*>(views[v].visbuffer);
+        d.W = views[v].width;
+        d.H = views[v].height;
+        d.hW = 0.5f * (float)views[v].width;
+        d.hH = 0.5f * (float)views[v].height;
+        d.near_plane = views[v].near_plane;
+        d.pad = 0;
+        P.total_pixels += (uint64_t)d.W * (uint64_t)d.H;
+    }
+    P.meshes.resize(M);
+    uint64_t base = 0;
+    for (uint32_t m = 0; m < M; ++m) {
+        const curast_mesh& me = meshes[m];
+        MeshDesc& md = P.meshes[m];
+        md.pos = me.vertices;
+        md.idx = me.indices;
+        md.T = me.num_triangles;
+        md.V = me.num_vertices;
+        md.pad = 0;
+        const uint32_t ni = n_inst(me);
+        const uint32_t draw_begin = (uint32_t)P.draws.size();
+        for (uint32_t i = 0; i < ni; ++i, base += me.num_triangles) {
+            if (me.num_triangles == 0) continue;
+            for (uint32_t v = 0; v < n_views; ++v) {
+                DrawDesc D;
+                draw_matrix(views[v].view_proj, me.instances ? me.instances + 12ull * i : nullptr, D.A);
+                if (cull && sphere_outside(D.A, me.bsphere, views[v].near_plane)) {
+                    P.draws_culled++;
+                    continue;
+                }
+                D.id_base = base;
+                D.view = v;
+                D.mesh = m;
+                P.draws.push_back(D);
+            }
+        }
+        const uint32_t dc = (uint32_t)P.draws.size() - draw_begin;
+        const uint64_t tbatches = (me.num_triangles + bt - 1) / bt;
+        if (me.num_triangles) {
+            const uint64_t all = (uint64_t)ni * n_views;
+            P.max_draws += all;
+            P.max_batches += tbatches * ((all + dpi - 1) / dpi);
+        }
+        if (dc && me.num_triangles) {
+            Segment s{};
+            s.batch_begin = P.hdr.total_batches;
+            s.mesh = m;
+            s.draw_begin = draw_begin;
+            s.draw_count = dc;
+            s.n_groups = (dc + dpi - 1) / dpi;
+            P.segs.push_back(s);
+            P.hdr.total_batches += tbatches * s.n_groups;
+            P.tri_draws += me.num_triangles * (uint64_t)dc;
+        }
+    }
+    P.hdr.n_segs = (uint32_t)P.segs.size();
+    P.hdr.n_views = n_views;
+    P.hdr.batch_tris = bt;
+    P.hdr.draws_per_item = dpi;
+    P.off_views = align_up(sizeof(FrameHeader), 256);
+    P.off_meshes = align_up(P.off_views + sizeof(ViewDesc) * n_views, 256);
+    P.off_segs = align_up(P.off_meshes + sizeof(MeshDesc) * std::max<uint32_t>(M, 1), 256);
+    P.off_draws = align_up(P.off_segs + sizeof(Segment) * std::max<uint32_t>(M, 1), 256);
+    P.bytes = align_up(P.off_draws + sizeof(DrawDesc) * std::max<size_t>(P.draws.size(), 1), 256);
+    P.max_bytes = align_up(P.off_draws + sizeof(DrawDesc) * std::max<size_t>(P.max_draws, 1), 256);
+    return CURAST_OK;
+}
+
+void write_plan(const Plan& P, void* host)
+{
+    char* h = static_cast<char*>(host);
+    std::memcpy(h, &P.hdr, sizeof(FrameHeader));
+    std::memcpy(h + P.off_views, P.views.data(), sizeof(ViewDesc) * P.views.size());
+    if (!P.meshes.empty()) std::memcpy(h + P.off_meshes, P.meshes.data(), sizeof(MeshDesc) * P.meshes.size());
+    if (!P.segs.empty()) std::memcpy(h + P.off_segs, P.segs.data(), sizeof(Segment) * P.segs.size());
+    if (!P.draws.empty()) std::memcpy(h + P.off_draws, P.draws.data(), sizeof(DrawDesc) * P.draws.size());
+}
+
+RasterArgs make_args(curast_ctx* ctx, const Plan& P)
+{
+    char* d = static_cast<char*>(ctx->raster_stage.dev);
+    RasterArgs a;
+    a.hdr = reinterpret_cast<const FrameHeader*>(d);
+    a.views = reinterpret_cast<const ViewDesc*>(d + P.off_views);
+    a.meshes = reinterpret_cast<const MeshDesc*>(d + P.off_meshes);
+    a.segs = reinterpret_cast<const Segment*>(d + P.off_segs);
+    a.draws = reinterpret_cast<const DrawDesc*>(d + P.off_draws);
+    a.q2 = ctx->q2;
+    a.large = ctx->large;
+    a.q3 = ctx->q3;
+    a.counters = ctx->counters;
+    a.stats = ctx->stats;
+    const bool zero = ctx->opt.flags & kFlagZeroQueues;
+    a.q2_cap = zero ? 0 : ctx->opt.q2_capacity;
+    a.large_cap = zero ? 0 : ctx->opt.large_capacity;
+    a.q3_cap = zero ? 0 : ctx->opt.q3_capacity;
+    a.small_px = ctx->opt.small_px;
+    a.medium_px = ctx->opt.medium_px;
+    a.flags = ctx->opt.flags;
+    return a;
+}
+
+TimedFrame* begin_timing(curast_ctx* ctx)
+{
+    if (!(ctx->opt.flags & CURAST_FLAG_TIMING)) return nullptr;
+    TimedFrame f;
+    for (int i = 0; i <= kNumSlots; ++i) hipEventCreate(&f.ev[i]);
+    for (int i = 0; i < kNumSlots; ++i) f.used[i] = 0;
+    ctx->timed.push_back(f);
+    return &ctx->timed.back();
+}
+
+// Launch the device part of a frame: clear, stage 1, overflow pass, stage 2, stage 3.
+int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, hipStream_t s, TimedFrame* tf)
+{
+    const RasterArgs a = make_args(ctx, P);
+    const bool stats = ctx->opt.flags & kFlagStats;
+    const uint32_t cus = (uint32_t)ctx->cus;
+    const uint64_t pairs = (P.total_pixels + 1) / 2;
+    const uint32_t clear_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((pairs + 255) / 256, cus * 16ull));
+    hipError_t e;
+    if (tf) hipEventRecord(tf->ev[0], s);
+    e = launch_clear(a, clear_grid, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "clear kernel launch");
+    if (tf) hipEventRecord(tf->ev[1], s);
+    e = launch_stage1(a, ctx->opt.s1_block, ctx->opt.s1_tris_per_thread, stats, std::max<uint32_t>(grid1, 1), s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 kernel launch");
+    if (tf) hipEventRecord(tf->ev[2], s);
+    e = launch_stage1_overflow(a, cus * 4, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 overflow kernel launch");
+    if (tf) hipEventRecord(tf->ev[3], s);
+    e = launch_stage2(a, std::max<uint32_t>(1, ctx->opt.s2_waves / 4), stats, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stage-2 kernel launch");
+    if (tf) hipEventRecord(tf->ev[4], s);
+    e = launch_stage3(a, std::max<uint32_t>(1, ctx->opt.s3_blocks), stats, s);
+    if (e != hipSuccess) return hip_fail(ctx, e, "stage-3 kernel launch");
+    if (tf) {
+        hipEventRecord(tf->ev[5], s);
+        for (int i = kTClear; i <= kTS3; ++i) tf->used[i] = 1;
+    }
+    return CURAST_OK;
+}
+
+uint32_t grid_for(uint64_t batches) { return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(batches, 1), 1ull << 24); }
+
+int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* views, uint32_t n_views,
+                   hipStream_t s, bool use_graph)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    Plan P;
+    int rc = build_plan(ctx, meshes, M, views, n_views, P);
+    if (rc) return rc;
+    rc = ensure_queues(ctx);
+    if (rc) return rc;
+    const size_t bytes = use_graph ? P.max_bytes : P.bytes;
+    rc = ensure_staging(ctx, ctx->raster_stage, bytes);
+    if (rc) return rc;
+    write_plan(P, ctx->raster_stage.host);
+    ctx->draws_culled += P.draws_culled;
+    TimedFrame* tf = begin_timing(ctx);
+    if (!use_graph) {
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->raster_stage.dev, ctx->raster_stage.host, P.bytes, hipMemcpyHostToDevice, s));
+        HIP_TRY(ctx, hipEventRecord(ctx->raster_stage.ev, s));
+        ctx->raster_stage.pending = true;
+        rc = launch_frame(ctx, P, grid_for(P.hdr.total_batches), s, tf);
+        return rc;
+    }
+    // graph path: one captured sequence per structure (sizes of the descriptor block, grid bound,
+    // options); replays copy the new descriptor contents from the same pinned buffer
+    const uint32_t grid1 = grid_for(P.max_batches);
+    uint64_t key[8] = {(uint64_t)M, (uint64_t)n_views, (uint64_t)P.max_bytes, (uint64_t)grid1,
+                       ((uint64_t)ctx->opt.s1_block << 32) | ctx->opt.s1_tris_per_thread,
+                       ((uint64_t)ctx->opt.s2_waves << 32) | ctx->opt.s3_blocks,
+                       ((uint64_t)ctx->opt.flags << 32) | ctx->opt.small_px,
+                       ((uint64_t)ctx->opt.medium_px << 32) | ctx->opt.s1_draws_per_item};
+    GraphEntry* ge = nullptr;
+    for (auto& g : ctx->graphs)
+        if (std::memcmp(g.key, key, sizeof key) == 0) ge = &g;
+    if (!ge) {
+        GraphEntry g;
+        std::memcpy(g.key, key, sizeof key);
+        HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = hipMemcpyAsync(ctx->raster_stage.dev, ctx->raster_stage.host, P.max_bytes, hipMemcpyHostToDevice,
+                                      ctx->capture_stream);
+        int lrc = e == hipSuccess ? launch_frame(ctx, P, grid1, ctx->capture_stream, nullptr) : hip_fail(ctx, e, "capture memcpy");
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &graph);
+        if (lrc) {
+            if (graph) hipGraphDestroy(graph);
+            return lrc;
+        }
+        if (e2 != hipSuccess) return hip_fail(ctx, e2, "hipStreamEndCapture");
+        g.graph = graph;
+        e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(graph);
+            return hip_fail(ctx, e, "hipGraphInstantiate");
+        }
+        ctx->graphs.push_back(g);
+        ge = &ctx->graphs.back();
+    }
+    if (tf) HIP_TRY(ctx, hipEventRecord(tf->ev[0], s));
+    HIP_TRY(ctx, hipGraphLaunch(ge->exec, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->raster_stage.ev, s));
+    ctx->raster_stage.pending = true;
+    if (tf) {
+        HIP_TRY(ctx, hipEventRecord(tf->ev[kNumSlots], s));
+        tf->used[kTFrame] = 1;
+    }
+    return CURAST_OK;
+}
+
+void collect_timings(curast_ctx* ctx)
+{
+    for (auto& f : ctx->timed) {
+        hipEventSynchronize(f.ev[kNumSlots]);
+        hipEventSynchronize(f.ev[5]);
+        float ms = 0.0f;
+        if (f.used[kTClear]) {
+            for (int i = kTClear; i <= kTS3; ++i)
+                if (hipEventElapsedTime(&ms, f.ev[i], f.ev[i + 1]) == hipSuccess) ctx->stage_ms[i] += ms;
+            if (hipEventElapsedTime(&ms, f.ev[0], f.ev[5]) == hipSuccess) ctx->stage_ms[kTFrame] += ms;
+        } else if (f.used[kTFrame]) {
+            if (hipEventElapsedTime(&ms, f.ev[0], f.ev[kNumSlots]) == hipSuccess) ctx->stage_ms[kTFrame] += ms;
+        }
+        if (f.used[kTResolve] || f.used[kTResolveBwd]) {
+            const int slot = f.used[kTResolve] ? kTResolve : kTResolveBwd;
+            if (hipEventElapsedTime(&ms, f.ev[6], f.ev[7]) == hipSuccess) ctx->stage_ms[slot] += ms;
+        }
+        if (f.used[kTClear] || f.used[kTFrame]) ctx->timed_frames++;
+        for (int i = 0; i <= kNumSlots; ++i) hipEventDestroy(f.ev[i]);
+    }
+    ctx->timed.clear();
+}
+
+int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view& view,
+                       const float* const* attrs, ResolveArgs& a, size_t& bytes_out)
+{
+    uint64_t np = 0;
+    for (uint32_t m = 0; m < M; ++m) np += n_inst(meshes[m]);
+    if (np > 0xFFFFFFF0ull) return fail(ctx, CURAST_E_INVALID, "too many (mesh, instance) pairs");
+    const size_t off_bases = 0;
+    const size_t off_pairs = align_up(sizeof(uint64_t) * (np + 1), 256);
+    const size_t off_meshes = align_up(off_pairs + sizeof(DrawDesc) * std::max<uint64_t>(np, 1), 256);
+    const size_t off_attrs = align_up(off_meshes + sizeof(MeshDesc) * std::max<uint32_t>(M, 1), 256);
+    const size_t bytes = align_up(off_attrs + sizeof(float*) * std::max<uint32_t>(M, 1), 256);
+    int rc = ensure_staging(ctx, ctx->resolve_stage, bytes);
+    if (rc) return rc;
+    char* h = static_cast<char*>(ctx->resolve_stage.host);
+    uint64_t* bases = reinterpret_cast<uint64_t*>(h + off_bases);
+    DrawDesc* pairs = reinterpret_cast<DrawDesc*>(h + off_pairs);
+    MeshDesc* md = reinterpret_cast<MeshDesc*>(h + off_meshes);
+    const float** ap = reinterpret_cast<const float**>(h + off_attrs);
+    uint64_t base = 0, p = 0;
+    for (uint32_t m = 0; m < M; ++m) {
+        md[m].pos = meshes[m].vertices;
+        md[m].idx = meshes[m].indices;
+        md[m].T = meshes[m].num_triangles;
+        md[m].V = meshes[m].num_vertices;
+        md[m].pad = 0;
+        ap[m] = attrs[m];
+        for (uint32_t i = 0; i < n_inst(meshes[m]); ++i, ++p) {
+            bases[p] = base;
+            draw_matrix(view.view_proj, meshes[m].instances ? meshes[m].instances + 12ull * i : nullptr, pairs[p].A);
+            pairs[p].id_base = base;
+            pairs[p].view = 0;
+            pairs[p].mesh = m;
+            base += meshes[m].num_triangles;
+        }
+    }
+    bases[np] = base;
+    char* d = static_cast<char*>(ctx->resolve_stage.dev);
+    a.vis = reinterpret_cast<const unsigned long long*>(view.visbuffer);
+    a.W = view.width;
+    a.H = view.height;
+    a.hW = 0.5f * (float)view.width;
+    a.hH = 0.5f * (float)view.height;
+    a.bases = reinterpret_cast<const uint64_t*>(d + off_bases);
+    a.pairs = reinterpret_cast<const DrawDesc*>(d + off_pairs);
+    a.meshes = reinterpret_cast<const MeshDesc*>(d + off_meshes);
+    a.attrs = reinterpret_cast<const float* const*>(d + off_attrs);
+    a.n_pairs = (uint32_t)np;
+    bytes_out = bytes;
+    return CURAST_OK;
+}
+
+int check_screen(curast_ctx* ctx, const uint64_t* vis, int32_t W, int32_t H, const uint32_t* idx, uint64_t T,
+                 const float* pos_ss, uint32_t V, const float* attrs, uint32_t C)
+{
+    if (!vis || !pos_ss || !attrs || (T && !idx)) return fail(ctx, CURAST_E_INVALID, "NULL pointer argument");
+    if (W < 1 || H < 1 || W > kMaxDim || H > kMaxDim) return fail(ctx, CURAST_E_INVALID, "width/height must lie in [1, 16384]");
+    if (C < 1 || C > 16) return fail(ctx, CURAST_E_INVALID, "C must lie in [1, 16]");
+    if (V == 0) return fail(ctx, CURAST_E_INVALID, "num_vertices must be > 0");
+    return CURAST_OK;
+}
+
+}  // namespace
+
+// ================================================================================================
+// C ABI
+// ================================================================================================
+extern "C" {
+
+int curast_version(void) { return 10000; }
+
+const char* curast_status_string(int status)
+{
+    switch (status) {
+    case CURAST_OK: return "ok";
+    case CURAST_E_INVALID: return "invalid argument";
+    case CURAST_E_ID_RANGE: return "triangle IDs exceed 36 bits";
+    case CURAST_E_OOM: return "out of memory";
+    case CURAST_E_HIP: return "HIP runtime error";
+    case CURAST_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char* curast_last_error(const curast_ctx* ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+int curast_create(const curast_options* opt, curast_ctx** out)
+{
+    if (!out) return CURAST_E_INVALID;
+    *out = nullptr;
+    curast_options u{};
+    if (opt) u = *opt;
+    std::string msg;
+    if (validate_options(u, msg)) return CURAST_E_INVALID;
+    curast_ctx* ctx = new (std::nothrow) curast_ctx();
+    if (!ctx) return CURAST_E_OOM;
+    auto cleanup = [&](int rc) {
+        curast_destroy(ctx);
+        return rc;
+    };
+    if (hipGetDevice(&ctx->device) != hipSuccess) return cleanup(CURAST_E_HIP);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess) return cleanup(CURAST_E_HIP);
+    ctx->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    ctx->user = u;
+    ctx->opt = resolve_defaults(u, ctx->cus);
+    if (hipMalloc(&ctx->counters, sizeof(unsigned long long) * kNumCounters) != hipSuccess) return cleanup(CURAST_E_OOM);
+    if (hipMalloc(&ctx->stats, sizeof(unsigned long long) * kNumStats) != hipSuccess) return cleanup(CURAST_E_OOM);
+    if (hipMemset(ctx->counters, 0, sizeof(unsigned long long) * kNumCounters) != hipSuccess) return cleanup(CURAST_E_HIP);
+    if (hipMemset(ctx->stats, 0, sizeof(unsigned long long) * kNumStats) != hipSuccess) return cleanup(CURAST_E_HIP);
+    if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess) return cleanup(CURAST_E_HIP);
+    if (hipEventCreateWithFlags(&ctx->raster_stage.ev, hipEventDisableTiming) != hipSuccess) return cleanup(CURAST_E_HIP);
+    if (hipEventCreateWithFlags(&ctx->resolve_stage.ev, hipEventDisableTiming) != hipSuccess) return cleanup(CURAST_E_HIP);
+    if (ensure_queues(ctx)) return cleanup(CURAST_E_OOM);
+    *out = ctx;
+    return CURAST_OK;
+}
+
+int curast_destroy(curast_ctx* ctx)
+{
+    if (!ctx) return CURAST_OK;
+    hipSetDevice(ctx->device);
+    hipDeviceSynchronize();
+    collect_timings(ctx);
+    drop_graphs(ctx);
+    for (Staging* st : {&ctx->raster_stage, &ctx->resolve_stage}) {
+        if (st->host) hipHostFree(st->host);
+        if (st->dev) hipFree(st->dev);
+        if (st->ev) hipEventDestroy(st->ev);
+    }
+    if (ctx->q2) hipFree(ctx->q2);
+    if (ctx->q3) hipFree(ctx->q3);
+    if (ctx->large) hipFree(ctx->large);
+    if (ctx->counters) hipFree(ctx->counters);
+    if (ctx->stats) hipFree(ctx->stats);
+    if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
+    delete ctx;
+    return CURAST_OK;
+}
+
+int curast_set_options(curast_ctx* ctx, const curast_options* opt)
+{
+    if (!ctx || !opt) return CURAST_E_INVALID;
+    std::string msg;
+    if (validate_options(*opt, msg)) return fail(ctx, CURAST_E_INVALID, msg);
+    ctx->user = *opt;
+    ctx->opt = resolve_defaults(*opt, ctx->cus);
+    return ensure_queues(ctx);
+}
+
+int curast_get_options(const curast_ctx* ctx, curast_options* opt)
+{
+    if (!ctx || !opt) return CURAST_E_INVALID;
+    *opt = ctx->opt;
+    return CURAST_OK;
+}
+
+int curast_rasterize_meshes(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* view, void* stream)
+{
+    if (!ctx || !view) return ctx ? fail(ctx, CURAST_E_INVALID, "view is NULL") : CURAST_E_INVALID;
+    return rasterize_impl(ctx, meshes, M, view, 1, static_cast<hipStream_t>(stream), false);
+}
+
+int curast_rasterize(curast_ctx* ctx, const float* vertices, uint32_t num_vertices, const uint32_t* indices,
+                     uint64_t num_triangles, const float* instances, uint32_t num_instances, const float view_proj[16],
+                     float near_plane, int32_t width, int32_t height, uint64_t* visbuffer, void* stream)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    if (!view_proj) return fail(ctx, CURAST_E_INVALID, "view_proj is NULL");
+    curast_mesh m{};
+    m.vertices = vertices;
+    m.num_vertices = num_vertices;
+    m.indices = indices;
+    m.num_triangles = num_triangles;
+    m.instances = instances;
+    m.num_instances = num_instances;
+    curast_view v{};
+    std::memcpy(v.view_proj, view_proj, sizeof(float) * 16);
+    v.near_plane = near_plane;
+    v.width = width;
+    v.height = height;
+    v.visbuffer = visbuffer;
+    return rasterize_impl(ctx, &m, 1, &v, 1, static_cast<hipStream_t>(stream), false);
+}
+
+int curast_rasterize_batched(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* views,
+                             uint32_t n_views, void* stream)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    const bool graph = !(ctx->opt.flags & kFlagNoGraph);
+    return rasterize_impl(ctx, meshes, M, views, n_views, static_cast<hipStream_t>(stream), graph);
+}
+
+int curast_project(curast_ctx* ctx, const curast_mesh* mesh, uint32_t instance, const curast_view* view, float* pos_ss,
+                   void* stream)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    if (!mesh || !view || !pos_ss) return fail(ctx, CURAST_E_INVALID, "NULL pointer argument");
+    int rc = check_view(ctx, *view, false);
+    if (rc) return rc;
+    rc = check_mesh(ctx, *mesh);
+    if (rc) return rc;
+    if (instance >= n_inst(*mesh)) return fail(ctx, CURAST_E_INVALID, "instance out of range");
+    if (mesh->num_vertices && !mesh->vertices) return fail(ctx, CURAST_E_INVALID, "vertices is NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    float A[12];
+    draw_matrix(view->view_proj, mesh->instances ? mesh->instances + 12ull * instance : nullptr, A);
+    HIP_TRY(ctx, launch_project(mesh->vertices, mesh->num_vertices, A, 0.5f * (float)view->width,
+                                0.5f * (float)view->height, pos_ss, static_cast<hipStream_t>(stream)));
+    return CURAST_OK;
+}
+
+int curast_resolve(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* view,
+                   const float* const* attrs, uint32_t C, float* out, void* stream)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    if (!view || !out || (M && (!meshes || !attrs))) return fail(ctx, CURAST_E_INVALID, "NULL pointer argument");
+    if (C < 1 || C > 16) return fail(ctx, CURAST_E_INVALID, "C must lie in [1, 16]");
+    int rc = check_view(ctx, *view);
+    if (rc) return rc;
+    uint64_t total = 0;
+    for (uint32_t m = 0; m < M; ++m) {
+        rc = check_mesh(ctx, meshes[m]);
+        if (rc) return rc;
+        if (meshes[m].num_triangles && !attrs[m]) return fail(ctx, CURAST_E_INVALID, "attrs[m] is NULL");
+        total += meshes[m].num_triangles * (uint64_t)n_inst(meshes[m]);
+        if (total > kMaxIds) return fail(ctx, CURAST_E_ID_RANGE, "more than 2^36 triangle instances");
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ResolveArgs a{};
+    size_t bytes = 0;
+    rc = build_resolve_desc(ctx, meshes, M, *view, attrs, a, bytes);
+    if (rc) return rc;
+    a.C = C;
+    a.out = out;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->resolve_stage.dev, ctx->resolve_stage.host, bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->resolve_stage.ev, s));
+    ctx->resolve_stage.pending = true;
+    TimedFrame* tf = begin_timing(ctx);
+    if (tf) hipEventRecord(tf->ev[6], s);
+    HIP_TRY(ctx, launch_resolve(a, s));
+    if (tf) {
+        hipEventRecord(tf->ev[7], s);
+        tf->used[kTResolve] = 1;
+    }
+    return CURAST_OK;
+}
+
+int curast_resolve_screen(curast_ctx* ctx, const uint64_t* visbuffer, int32_t width, int32_t height,
+                          const uint32_t* indices, uint64_t num_triangles, uint64_t id_base, const float* pos_ss,
+                          uint32_t num_vertices, const float* attrs, uint32_t C, float* out, void* stream)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    int rc = check_screen(ctx, visbuffer, width, height, indices, num_triangles, pos_ss, num_vertices, attrs, C);
+    if (rc) return rc;
+    if (!out) return fail(ctx, CURAST_E_INVALID, "out is NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    ScreenArgs a{};
+    a.vis = reinterpret_cast<const unsigned long long*>(visbuffer);
+    a.W = width;
+    a.H = height;
+    a.idx = indices;
+    a.T = num_triangles;
+    a.id_base = id_base;
+    a.pos_ss = pos_ss;
+    a.V = num_vertices;
+    a.attrs = attrs;
+    a.C = C;
+    a.out = out;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TimedFrame* tf = begin_timing(ctx);
+    if (tf) hipEventRecord(tf->ev[6], s);
+    HIP_TRY(ctx, launch_resolve_screen(a, s));
+    if (tf) {
+        hipEventRecord(tf->ev[7], s);
+        tf->used[kTResolve] = 1;
+    }
+    return CURAST_OK;
+}
+
+int curast_resolve_backward(curast_ctx* ctx, const uint64_t* visbuffer, int32_t width, int32_t height,
+                            const uint32_t* indices, uint64_t num_triangles, uint64_t id_base, const float* pos_ss,
+                            uint32_t num_vertices, const float* attrs, uint32_t C, const float* grad_out,
+                            float* grad_attr, float* grad_pos, void* stream)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    int rc = check_screen(ctx, visbuffer, width, height, indices, num_triangles, pos_ss, num_vertices, attrs, C);
+    if (rc) return rc;
+    if (!grad_out || !grad_attr) return fail(ctx, CURAST_E_INVALID, "grad_out and grad_attr are required");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    ScreenArgs a{};
+    a.vis = reinterpret_cast<const unsigned long long*>(visbuffer);
+    a.W = width;
+    a.H = height;
+    a.idx = indices;
+    a.T = num_triangles;
+    a.id_base = id_base;
+    a.pos_ss = pos_ss;
+    a.V = num_vertices;
+    a.attrs = attrs;
+    a.C = C;
+    a.grad_out = grad_out;
+    a.grad_attr = grad_attr;
+    a.grad_pos = grad_pos;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    TimedFrame* tf = begin_timing(ctx);
+    if (tf) hipEventRecord(tf->ev[6], s);
+    HIP_TRY(ctx, launch_resolve_backward(a, s));
+    if (tf) {
+        hipEventRecord(tf->ev[7], s);
+        tf->used[kTResolveBwd] = 1;
+    }
+    return CURAST_OK;
+}
+
+int curast_get_stats(curast_ctx* ctx, curast_stats* out)
+{
+    if (!ctx || !out) return CURAST_E_INVALID;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    unsigned long long s[kNumStats];
+    HIP_TRY(ctx, hipMemcpy(s, ctx->stats, sizeof s, hipMemcpyDeviceToHost));
+    std::memset(out, 0, sizeof *out);
+    out->tri_draws = s[kStTriDraws];
+    out->draws_culled = ctx->draws_culled;
+    out->culled_near = s[kStCulledNear];
+    out->culled_frustum = s[kStCulledFrustum];
+    out->culled_tiny = s[kStCulledTiny];
+    out->culled_backface = s[kStCulledBack];
+    out->s1_rasterized = s[kStS1Raster];
+    out->q2_entries = s[kStQ2];
+    out->q2_overflow = s[kStQ2Overflow];
+    out->s2_rasterized = s[kStS2Raster];
+    out->q3_entries = s[kStQ3];
+    out->q3_overflow = s[kStQ3Overflow];
+    out->fragments = s[kStFragments];
+    out->atomics = s[kStAtomics];
+    return CURAST_OK;
+}
+
+int curast_reset_stats(curast_ctx* ctx)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    HIP_TRY(ctx, hipMemset(ctx->stats, 0, sizeof(unsigned long long) * kNumStats));
+    ctx->draws_culled = 0;
+    return CURAST_OK;
+}
+
+int curast_get_stage_times(curast_ctx* ctx, double* ms, uint64_t* frames)
+{
+    if (!ctx || !ms) return CURAST_E_INVALID;
+    collect_timings(ctx);
+    for (int i = 0; i < kNumSlots; ++i) ms[i] = ctx->stage_ms[i];
+    if (frames) *frames = ctx->timed_frames;
+    return CURAST_OK;
+}
+
+int curast_reset_stage_times(curast_ctx* ctx)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    collect_timings(ctx);
+    for (int i = 0; i < kNumSlots; ++i) ctx->stage_ms[i] = 0.0;
+    ctx->timed_frames = 0;
+    return CURAST_OK;
+}
+
+// Queue fill of the last frame (internal, used by the autotuner): Q2, large records, Q3.
+int curast_internal_queue_counts(curast_ctx* ctx, uint64_t out[3])
+{
+    if (!ctx || !out) return CURAST_E_INVALID;
+    HIP_TRY(ctx, hipDeviceSynchronize());
+    unsigned long long c[kNumCounters];
+    HIP_TRY(ctx, hipMemcpy(c, ctx->counters, sizeof c, hipMemcpyDeviceToHost));
+    out[0] = c[kCntQ2];
+    out[1] = c[kCntLarge];
+    out[2] = c[kCntQ3];
+    return CURAST_OK;
+}
+
+int curast_internal_num_cus(const curast_ctx* ctx) { return ctx ? ctx->cus : 0; }
+
+int64_t curast_id_bases(const curast_mesh* meshes, uint32_t M, int64_t* bases)
+{
+    if (M && !meshes) return CURAST_E_INVALID;
+    int64_t p = 0;
+    uint64_t acc = 0;
+    for (uint32_t m = 0; m < M; ++m) {
+        if (meshes[m].instances && meshes[m].num_instances == 0) return CURAST_E_INVALID;
+        for (uint32_t i = 0; i < n_inst(meshes[m]); ++i) {
+            if (bases) bases[p] = (int64_t)acc;
+            ++p;
+            acc += meshes[m].num_triangles;
+        }
+    }
+    if (acc > kMaxIds) return CURAST_E_ID_RANGE;
+    if (bases) bases[p] = (int64_t)acc;
+    return p;
+}
+
+}  // extern "C"
