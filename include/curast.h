@@ -91,6 +91,10 @@ typedef struct {
     uint32_t q3_capacity;       /* stage-2 -> stage-3 tile parts (default 1M); overflow as above */
     uint32_t large_capacity;    /* large (sub-)triangle records for stage 3 (default 256K) */
     uint32_t flags;             /* CURAST_FLAG_* */
+    uint32_t s1_mode;           /* stage-1 kernel: 0 = auto (currently 2), 1 = one lane per
+                                   triangle with exact arithmetic only, 2 = conservative fast reject
+                                   with approximate reciprocals and wave-compacted exact work,
+                                   3 = same as 2 (reserved) */
 } curast_options;
 
 typedef struct {
@@ -235,6 +239,17 @@ int curast_reset_stats(curast_ctx* ctx);
    of rasterized frames timed.  Batched (graph) frames contribute only the whole-frame time. */
 int curast_get_stage_times(curast_ctx* ctx, double ms[8], uint64_t* frames);
 int curast_reset_stage_times(curast_ctx* ctx);
+
+/*
+ * Host-side frame planning only (no GPU; Sec. 4 host mesh list): validates the arguments as the
+ * rasterize calls do and reports which (mesh, instance, view) draws survive the conservative
+ * bounding-sphere frustum cull.  visible: host [pairs][n_views] bytes (1 = drawn) or NULL;
+ * bases: host [pairs + 1] exclusive prefix of triangle counts or NULL; counts: host [4] = draws
+ * kept, draws culled, stage-1 work items, triangle x draw items, or NULL.  Views' visbuffer
+ * pointers must be non-NULL but are not touched.
+ */
+int curast_plan(const curast_mesh* meshes, uint32_t M, const curast_view* views, uint32_t n_views,
+                const curast_options* opt, uint8_t* visible, int64_t* bases, uint64_t counts[4]);
 
 /* Exclusive prefix of triangle counts over all (mesh, instance) pairs (host only, no GPU):
    bases host [pairs + 1]; returns the number of pairs (>= 0) or a negative status. */

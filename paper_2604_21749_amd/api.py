@@ -41,7 +41,7 @@ class CurastError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [(n, C.c_uint32) for n in (
         "small_px", "medium_px", "s1_block", "s1_tris_per_thread", "s1_draws_per_item", "s2_waves",
-        "s3_blocks", "q2_capacity", "q3_capacity", "large_capacity", "flags")]
+        "s3_blocks", "q2_capacity", "q3_capacity", "large_capacity", "flags", "s1_mode")]
 
 
 class MeshStruct(C.Structure):
@@ -85,6 +85,7 @@ SIGNATURES = {
     "curast_get_stage_times": (C.c_int, [_P, C.POINTER(C.c_double), C.POINTER(C.c_uint64)]),
     "curast_reset_stage_times": (C.c_int, [_P]),
     "curast_id_bases": (C.c_int64, [_P, C.c_uint32, _P]),
+    "curast_plan": (C.c_int, [_P, C.c_uint32, _P, C.c_uint32, C.POINTER(Options), _P, _P, _P]),
     "curast_status_string": (C.c_char_p, [C.c_int]),
     "curast_last_error": (C.c_char_p, [_P]),
     "curast_version": (C.c_int, []),
@@ -156,9 +157,10 @@ class GpuMesh:
         return GpuMesh(pos, idx, inst, bs, attrs)
 
 
-def _mesh_struct(m: GpuMesh, keep: list) -> MeshStruct:
-    _check_cuda(m.pos, torch.float32, "vertices", 3)
-    _check_cuda(m.idx, torch.int32, "indices", 3)
+def _mesh_struct(m: GpuMesh, keep: list, check: bool = True) -> MeshStruct:
+    if check:
+        _check_cuda(m.pos, torch.float32, "vertices", 3)
+        _check_cuda(m.idx, torch.int32, "indices", 3)
     s = MeshStruct()
     s.vertices = m.pos.data_ptr() if m.pos.numel() else None
     s.num_vertices = m.pos.shape[0]
@@ -404,13 +406,34 @@ class Context:
 def id_bases(meshes: Sequence[GpuMesh]) -> np.ndarray:
     """curast_id_bases (host only): exclusive prefix of triangle counts over (mesh, instance)."""
     keep = []
-    arr = (MeshStruct * max(1, len(meshes)))(*[_mesh_struct(m, keep) for m in meshes])
+    arr = (MeshStruct * max(1, len(meshes)))(*[_mesh_struct(m, keep, check=False) for m in meshes])
     n = lib().curast_id_bases(arr, len(meshes), None)
     if n < 0:
         raise CurastError(int(n), lib().curast_status_string(int(n)).decode())
     out = np.zeros(n + 1, np.int64)
     lib().curast_id_bases(arr, len(meshes), out.ctypes.data)
     return out
+
+
+def plan(meshes: Sequence[GpuMesh], views, **options):
+    """curast_plan (host only): (visible [pairs, n_views] bool, bases [pairs + 1], counts dict)."""
+    keep = []
+    arr = (MeshStruct * max(1, len(meshes)))(*[_mesh_struct(m, keep, check=False) for m in meshes])
+    dummy = (C.c_uint64 * max(1, len(views)))()     # distinct non-NULL buffers, never touched
+    vs = (ViewStruct * len(views))()
+    for i, v in enumerate(views):
+        vs[i] = _view_struct(v.vp, v.near, v.width, v.height, None)
+        vs[i].visbuffer = C.addressof(dummy) + 8 * i
+    pairs = sum(m.num_instances for m in meshes)
+    visible = np.zeros((pairs, len(views)), np.uint8)
+    bases = np.zeros(pairs + 1, np.int64)
+    counts = np.zeros(4, np.uint64)
+    opt = Context._options(options)
+    rc = lib().curast_plan(arr, len(meshes), vs, len(views), C.byref(opt), visible.ctypes.data, bases.ctypes.data,
+                           counts.ctypes.data)
+    if rc != OK:
+        raise CurastError(rc, lib().curast_status_string(rc).decode())
+    return visible.astype(bool), bases, dict(zip(("draws", "culled", "work_items", "tri_draws"), map(int, counts)))
 
 
 class ResolveFn(torch.autograd.Function):

@@ -60,6 +60,7 @@ const Field kFields[] = {
     {"q2_capacity", &curast_options::q2_capacity},
     {"q3_capacity", &curast_options::q3_capacity},
     {"large_capacity", &curast_options::large_capacity},
+    {"s1_mode", &curast_options::s1_mode},
 };
 
 std::string to_json(const std::string& key, const curast_options& o)
@@ -171,6 +172,7 @@ extern "C" int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint3
         std::vector<uint32_t> values;
     };
     std::vector<Axis> axes = {
+        {&curast_options::s1_mode, {0, 1, 2, 3}},
         {&curast_options::s1_block, {64, 128, 256, 512}},
         {&curast_options::s1_tris_per_thread, {1, 2, 4}},
         {&curast_options::small_px, {32, 64, 128, 256, 512}},

@@ -119,6 +119,7 @@ struct RasterArgs {
     uint32_t q2_cap, large_cap, q3_cap;
     uint32_t small_px, medium_px;
     uint32_t flags;
+    uint32_t s1_mode;             // 0 auto, 1 exact only, 2 fast reject, 3 fast reject + vertex sharing
 };
 
 struct ResolveArgs {

@@ -10,6 +10,25 @@
 
 namespace curast {
 
+// Caller buffers (vertices, indices, visibility buffers) are global memory; pointers fetched from
+// descriptors are generic to the compiler, which would emit flat accesses.  These casts give it
+// the address space so it emits global loads, stores and atomics.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define CURAST_GLOBAL __attribute__((address_space(1)))
+#else
+#define CURAST_GLOBAL
+#endif
+template <typename T>
+__device__ __forceinline__ const CURAST_GLOBAL T* gl(const T* p)
+{
+    return (const CURAST_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ CURAST_GLOBAL T* gl(T* p)
+{
+    return (CURAST_GLOBAL T*)p;
+}
+
 struct Clip {                 // clip-space vertex: x, y and the positive view depth w
     float x, y, w;
 };
@@ -127,11 +146,12 @@ __device__ __forceinline__ float frag_depth(float e0, float e1, float e2, const 
 
 __device__ __forceinline__ void write_fragment(unsigned long long* p, unsigned long long key, bool early_out)
 {
+    CURAST_GLOBAL unsigned long long* g = gl(p);
     if (early_out) {
-        const unsigned long long cur = *p;   // keys only decrease: a stale value is never smaller
+        const unsigned long long cur = *g;   // keys only decrease: a stale value is never smaller
         if (key >= cur) return;
     }
-    atomicMin(p, key);
+    atomicMin(g, key);
 }
 
 // General (int64) setup of a snapped triangle, used by stages 2 and 3 and the overflow paths.

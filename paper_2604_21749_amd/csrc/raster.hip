@@ -208,7 +208,24 @@ __global__ void __launch_bounds__(256) clear_kernel(RasterArgs a)
 // ----------------------------------------------------------------------------------------------
 // Stage 1: one lane per triangle, looping over the draws (instances x views) of its work item
 // ----------------------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t find_segment(const Segment* segs, uint32_t n_segs, uint64_t b)
+// Work-item values are the same on every lane; readfirstlane puts them in scalar registers so the
+// draw and view descriptors they index are fetched with scalar loads.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint64_t uni64(uint64_t v)
+{
+    return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32)) << 32) |
+           (uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+}
+
+struct WorkItem {
+    uint32_t mesh;
+    uint64_t tri_batch;
+    uint32_t d0, d1;
+};
+
+__device__ __forceinline__ WorkItem locate_work(const Segment* __restrict__ segs, uint32_t n_segs, uint32_t dpi, uint64_t b);
+
+__device__ __forceinline__ uint32_t find_segment(const Segment* __restrict__ segs, uint32_t n_segs, uint64_t b)
 {
     uint32_t lo = 0, hi = n_segs;
     while (hi - lo > 1) {
@@ -219,36 +236,64 @@ __device__ __forceinline__ uint32_t find_segment(const Segment* segs, uint32_t n
     return lo;
 }
 
-template <int BLOCK, int TPT, bool STATS>
-__global__ void __launch_bounds__(BLOCK) stage1_kernel(RasterArgs a)
+// Work item b -> (mesh, triangle batch, draw range), all uniform.
+__device__ __forceinline__ WorkItem locate_work(const Segment* __restrict__ segs, uint32_t n_segs, uint32_t dpi, uint64_t b)
 {
-    const uint64_t total = a.hdr->total_batches;
-    const uint32_t n_segs = a.hdr->n_segs;
-    const uint32_t dpi = a.hdr->draws_per_item;
+    const uint32_t si = uni(find_segment(segs, n_segs, b));
+    const Segment sg = segs[si];
+    const uint64_t begin = uni64(sg.batch_begin);
+    const uint32_t ng = uni(sg.n_groups);
+    const uint32_t db = uni(sg.draw_begin);
+    const uint32_t dc = uni(sg.draw_count);
+    const uint64_t j = b - begin;
+    WorkItem w;
+    w.mesh = uni(sg.mesh);
+    uint32_t g = 0;
+    if (ng == 1) {
+        w.tri_batch = j;
+    } else {
+        w.tri_batch = uni64(j / ng);
+        g = uni((uint32_t)(j - w.tri_batch * ng));
+    }
+    w.d0 = db + g * dpi;
+    w.d1 = min(db + dc, w.d0 + dpi);
+    return w;
+}
+
+#define CURAST_DESC_PARAMS                                                                       \
+    const FrameHeader* __restrict__ d_hdr, const ViewDesc* __restrict__ d_views,                  \
+        const MeshDesc* __restrict__ d_meshes, const Segment* __restrict__ d_segs,                \
+        const DrawDesc* __restrict__ d_draws
+#define CURAST_DESC_ARGS(a) (a).hdr, (a).views, (a).meshes, (a).segs, (a).draws
+
+template <int BLOCK, int TPT, bool STATS>
+__global__ void __launch_bounds__(BLOCK) stage1_kernel(RasterArgs a, CURAST_DESC_PARAMS)
+{
+    const FrameHeader hdr = *d_hdr;
+    const uint64_t total = uni64(hdr.total_batches);
+    const uint32_t n_segs = uni(hdr.n_segs);
+    const uint32_t dpi = uni(hdr.draws_per_item);
     const bool early_out = !(a.flags & kFlagNoEarlyOut);
     const bool tiny_cull = !(a.flags & kFlagNoTinyCull);
     StatAcc<STATS> st;
     for (uint64_t b = blockIdx.x; b < total; b += gridDim.x) {
-        const Segment seg = a.segs[find_segment(a.segs, n_segs, b)];
-        const uint64_t j = b - seg.batch_begin;
-        const uint64_t tb = j / seg.n_groups;
-        const uint32_t g = (uint32_t)(j - tb * seg.n_groups);
-        const uint32_t d0 = seg.draw_begin + g * dpi;
-        const uint32_t d1 = min(seg.draw_begin + seg.draw_count, d0 + dpi);
-        const MeshDesc mesh = a.meshes[seg.mesh];
+        const WorkItem wi = locate_work(d_segs, n_segs, dpi, b);
+        const uint64_t tb = wi.tri_batch;
+        const uint32_t d0 = wi.d0, d1 = wi.d1;
+        const MeshDesc mesh = d_meshes[wi.mesh];
 #pragma unroll 1
         for (int k = 0; k < TPT; ++k) {
             const uint64_t t = tb * (uint64_t)(BLOCK * TPT) + (uint64_t)(k * BLOCK) + threadIdx.x;
             bool valid = t < mesh.T;
             float p[9];
             if (valid) {
-                const uint32_t* ip = mesh.idx + 3 * t;
+                const CURAST_GLOBAL uint32_t* ip = gl(mesh.idx) + 3 * t;
                 const uint32_t i0 = ip[0], i1 = ip[1], i2 = ip[2];
                 valid = i0 < mesh.V && i1 < mesh.V && i2 < mesh.V;
                 if (valid) {
-                    const float* q0 = mesh.pos + 3 * (size_t)i0;
-                    const float* q1 = mesh.pos + 3 * (size_t)i1;
-                    const float* q2 = mesh.pos + 3 * (size_t)i2;
+                    const CURAST_GLOBAL float* q0 = gl(mesh.pos) + 3 * (size_t)i0;
+                    const CURAST_GLOBAL float* q1 = gl(mesh.pos) + 3 * (size_t)i1;
+                    const CURAST_GLOBAL float* q2 = gl(mesh.pos) + 3 * (size_t)i2;
                     p[0] = q0[0]; p[1] = q0[1]; p[2] = q0[2];
                     p[3] = q1[0]; p[4] = q1[1]; p[5] = q1[2];
                     p[6] = q2[0]; p[7] = q2[1]; p[8] = q2[2];
@@ -256,8 +301,8 @@ __global__ void __launch_bounds__(BLOCK) stage1_kernel(RasterArgs a)
             }
 #pragma unroll 1
             for (uint32_t d = d0; d < d1; ++d) {
-                const DrawDesc& D = a.draws[d];
-                const ViewDesc V = a.views[D.view];
+                const DrawDesc D = d_draws[d];
+                const ViewDesc V = d_views[D.view];
                 int route = kRouteNone;
                 SmallTri s;
                 if (valid) {
@@ -288,35 +333,227 @@ __global__ void __launch_bounds__(BLOCK) stage1_kernel(RasterArgs a)
     st.flush(a.stats);
 }
 
+// ----------------------------------------------------------------------------------------------
+// Stage 1, fast variant.  Two changes to the lane-per-triangle loop, neither of which changes a
+// single fragment:
+//  (1) a conservative reject with approximate window positions (v_rcp_f32 instead of the correctly
+//      rounded 1/w) and a bounding box widened by kFastMargin pixels: when the widened box holds no
+//      pixel centre inside the view, the exact box cannot hold one either, so the triangle is
+//      culled without the exact arithmetic (almost every triangle of a dense mesh ends here);
+//  (2) the few undecided triangles are appended to a list in LDS and run through the exact
+//      classification and rasterization together, so no lane idles while one lane of its
+//      wavefront takes the long path.
+// With SHARE, work items that draw the same triangles for several instances/views first
+// deduplicate the batch's vertex indices in an LDS hash table; each unique vertex is then
+// transformed once per draw instead of once per referencing triangle (vertex reuse through LDS).
+//
+// Error bound of the fast positions (|x|, |y| <= 2w, near <= w < 1e30, W, H <= 16384): rcp has
+// at most 1 ulp error, so |x*r - x/w| <= 2^-20 and the approximate window coordinate differs from
+// the exact snapped one by at most 1.625 hW 2^-20 + 2^-9 <= 0.0147 px, plus 2^-9 px of rounding
+// in the box arithmetic: below the margin of 1/32 px.
+// ----------------------------------------------------------------------------------------------
+constexpr float kFastMargin = 1.0f / 32.0f;
+constexpr float kFastGuard = 2.0f;
+
+__device__ __forceinline__ float2 fast_window(const Clip& c, const ViewDesc& V)
+{
+    const float g = kFastGuard * c.w;
+    if (!(c.w >= V.near_plane) || !(c.w < 1e30f) || __builtin_fabsf(c.x) > g || __builtin_fabsf(c.y) > g)
+        return make_float2(__builtin_nanf(""), 0.0f);
+    const float r = __builtin_amdgcn_rcpf(c.w);
+    return make_float2(__builtin_fmaf(c.x * r, V.hW, V.hW), __builtin_fmaf(c.y * r, V.hH, V.hH));
+}
+
+// True when the triangle provably covers no pixel centre of the view.
+__device__ __forceinline__ bool fast_reject(float2 a, float2 b, float2 c, const ViewDesc& V, bool tiny_cull)
+{
+    if (__builtin_isnan(a.x) || __builtin_isnan(b.x) || __builtin_isnan(c.x)) return false;
+    // centre of pixel p is p + 0.5: p in [ceil(min - m - 0.5), floor(max + m - 0.5)]
+    const float xlo = __builtin_ceilf(fminf(a.x, fminf(b.x, c.x)) - (kFastMargin + 0.5f));
+    const float xhi = __builtin_floorf(fmaxf(a.x, fmaxf(b.x, c.x)) + (kFastMargin - 0.5f));
+    const float ylo = __builtin_ceilf(fminf(a.y, fminf(b.y, c.y)) - (kFastMargin + 0.5f));
+    const float yhi = __builtin_floorf(fmaxf(a.y, fmaxf(b.y, c.y)) + (kFastMargin - 0.5f));
+    const float wmax = (float)(V.W - 1), hmax = (float)(V.H - 1);
+    if (xhi < 0.0f || xlo > wmax || yhi < 0.0f || ylo > hmax) return true;   // outside the view
+    if (!tiny_cull) return false;
+    return fmaxf(xlo, 0.0f) > fminf(xhi, wmax) || fmaxf(ylo, 0.0f) > fminf(yhi, hmax);
+}
+
+// Undecided (triangle, draw) pairs wait in a per-wavefront ring in LDS with their exact clip
+// coordinates; the wavefront drains 64 of them at a time with every lane busy.  Head and tail are
+// wave-uniform (scalar), so no workgroup barrier is needed.
+struct RingEntry {
+    float c[9];
+    uint32_t draw;
+    uint32_t tri;
+};
+constexpr int kRing = 128;
+
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Exact classification and rasterization of ring entries [head, head + n), n <= 64, one per lane.
+template <bool STATS>
+__device__ __forceinline__ void drain_ring(const RasterArgs& a, const ViewDesc* __restrict__ d_views,
+                                           const DrawDesc* __restrict__ d_draws, const RingEntry* ring,
+                                           uint32_t head, uint32_t n, bool tiny_cull, bool early_out,
+                                           StatAcc<STATS>& st)
+{
+    const uint32_t lane = lane_id();
+    int route = kRouteNone;
+    SmallTri s;
+    uint32_t dd = 0, tt = 0;
+    ViewDesc V;
+    uint64_t idb = 0;
+    if (lane < n) {
+        const RingEntry& e = ring[(head + lane) & (kRing - 1)];
+        dd = e.draw;
+        tt = e.tri;
+        const Clip c[3] = {{e.c[0], e.c[1], e.c[2]}, {e.c[3], e.c[4], e.c[5]}, {e.c[6], e.c[7], e.c[8]}};
+        const DrawDesc& D = d_draws[dd];
+        V = d_views[D.view];
+        idb = D.id_base;
+        route = classify<STATS>(c, V, a.small_px, tiny_cull, s, st);
+    }
+    const unsigned long long slot = wave_reserve(route == kRouteForward, a.counters + kCntQ2);
+    if (route == kRouteForward) {
+        st.add(kStQ2);
+        if (slot < a.q2_cap) {
+            Q2Entry qe;
+            qe.draw = dd;
+            qe.tri = tt;
+            a.q2[slot] = qe;
+        } else {
+            st.add(kStQ2Overflow);
+        }
+    }
+    if (route == kRouteSmall) {
+        st.add(kStS1Raster);
+        raster_small<STATS>(s, idb + tt, V, early_out, st);
+    }
+}
+
+template <int BLOCK, int TPT, bool STATS>
+__global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST_DESC_PARAMS)
+{
+    constexpr int WAVES = BLOCK / 64;
+    __shared__ RingEntry s_ring[WAVES][kRing];
+    const FrameHeader hdr = *d_hdr;
+    const uint64_t total = uni64(hdr.total_batches);
+    const uint32_t n_segs = uni(hdr.n_segs);
+    const uint32_t dpi = uni(hdr.draws_per_item);
+    const bool early_out = !(a.flags & kFlagNoEarlyOut);
+    const bool tiny_cull = !(a.flags & kFlagNoTinyCull);
+    RingEntry* ring = s_ring[threadIdx.x >> 6];
+    const uint32_t lane = lane_id();
+    uint32_t head = 0, tail = 0;   // wave-uniform
+    StatAcc<STATS> st;
+    for (uint64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const WorkItem wi = locate_work(d_segs, n_segs, dpi, b);
+        const uint64_t tb = wi.tri_batch;
+        const uint32_t d0 = wi.d0, d1 = wi.d1;
+        const MeshDesc mesh = d_meshes[wi.mesh];
+        // issue every index load, then every vertex load, before any use (memory parallelism)
+        uint32_t vi[TPT][3];
+        bool valid[TPT];
+        uint32_t tri[TPT];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            const uint64_t t = tb * (uint64_t)(BLOCK * TPT) + (uint64_t)(k * BLOCK) + threadIdx.x;
+            tri[k] = (uint32_t)t;
+            valid[k] = t < mesh.T;
+            const CURAST_GLOBAL uint32_t* ip = gl(mesh.idx) + 3 * (valid[k] ? t : 0);
+            vi[k][0] = ip[0];
+            vi[k][1] = ip[1];
+            vi[k][2] = ip[2];
+        }
+        float p[TPT][9];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            valid[k] = valid[k] && vi[k][0] < mesh.V && vi[k][1] < mesh.V && vi[k][2] < mesh.V;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const CURAST_GLOBAL float* q = gl(mesh.pos) + 3 * (size_t)(valid[k] ? vi[k][v] : 0);
+                p[k][3 * v + 0] = q[0];
+                p[k][3 * v + 1] = q[1];
+                p[k][3 * v + 2] = q[2];
+            }
+        }
+#pragma unroll 1
+        for (uint32_t d = d0; d < d1; ++d) {
+            const DrawDesc D = d_draws[d];
+            const ViewDesc V = d_views[D.view];
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+                const Clip c0 = transform(D.A, p[k][0], p[k][1], p[k][2]);
+                const Clip c1 = transform(D.A, p[k][3], p[k][4], p[k][5]);
+                const Clip c2 = transform(D.A, p[k][6], p[k][7], p[k][8]);
+                bool need = false;
+                if (valid[k]) {
+                    st.add(kStTriDraws);
+                    need = !fast_reject(fast_window(c0, V), fast_window(c1, V), fast_window(c2, V), V, tiny_cull);
+                    if (!need) st.add(kStCulledTiny);
+                }
+                const unsigned long long m = __ballot(need);
+                if (m) {
+                    if (need) {
+                        RingEntry& e = ring[(tail + rank_in(m)) & (kRing - 1)];
+                        e.c[0] = c0.x; e.c[1] = c0.y; e.c[2] = c0.w;
+                        e.c[3] = c1.x; e.c[4] = c1.y; e.c[5] = c1.w;
+                        e.c[6] = c2.x; e.c[7] = c2.y; e.c[8] = c2.w;
+                        e.draw = d;
+                        e.tri = tri[k];
+                    }
+                    tail += (uint32_t)__popcll(m);
+                    if (tail - head >= 64) {
+                        wave_lds_sync();
+                        drain_ring<STATS>(a, d_views, d_draws, ring, head, 64, tiny_cull, early_out, st);
+                        head += 64;
+                        wave_lds_sync();
+                    }
+                }
+            }
+        }
+    }
+    if (tail != head) {
+        wave_lds_sync();
+        drain_ring<STATS>(a, d_views, d_draws, ring, head, tail - head, tiny_cull, early_out, st);
+    }
+    (void)lane;
+    st.flush(a.stats);
+}
+
 // Stage-1 overflow pass: when more triangles were forwarded than Q2 holds, every forwarded
 // triangle is rasterized here by one thread (those that did fit are drawn twice; the minimum is
 // idempotent).  Exits at once when nothing overflowed.
-__global__ void __launch_bounds__(256) stage1_overflow_kernel(RasterArgs a)
+__global__ void __launch_bounds__(256) stage1_overflow_kernel(RasterArgs a, CURAST_DESC_PARAMS)
 {
     if (a.counters[kCntQ2] <= a.q2_cap) return;
-    const uint64_t total = a.hdr->total_batches;
-    const uint32_t n_segs = a.hdr->n_segs;
-    const uint32_t dpi = a.hdr->draws_per_item;
-    const uint32_t bt = a.hdr->batch_tris;
+    const FrameHeader hdr = *d_hdr;
+    const uint64_t total = uni64(hdr.total_batches);
+    const uint32_t n_segs = uni(hdr.n_segs);
+    const uint32_t dpi = uni(hdr.draws_per_item);
+    const uint32_t bt = uni(hdr.batch_tris);
     const bool early_out = !(a.flags & kFlagNoEarlyOut);
     const bool tiny_cull = !(a.flags & kFlagNoTinyCull);
     StatAcc<false> st;
     for (uint64_t b = blockIdx.x; b < total; b += gridDim.x) {
-        const Segment seg = a.segs[find_segment(a.segs, n_segs, b)];
-        const uint64_t j = b - seg.batch_begin;
-        const uint64_t tb = j / seg.n_groups;
-        const uint32_t g = (uint32_t)(j - tb * seg.n_groups);
-        const uint32_t d0 = seg.draw_begin + g * dpi;
-        const uint32_t d1 = min(seg.draw_begin + seg.draw_count, d0 + dpi);
-        const MeshDesc mesh = a.meshes[seg.mesh];
+        const WorkItem wi = locate_work(d_segs, n_segs, dpi, b);
+        const uint64_t tb = wi.tri_batch;
+        const uint32_t d0 = wi.d0, d1 = wi.d1;
+        const MeshDesc mesh = d_meshes[wi.mesh];
         for (uint32_t tt = threadIdx.x; tt < bt; tt += blockDim.x) {
             const uint64_t t = tb * bt + tt;
             if (t >= mesh.T) break;
             const uint32_t i0 = mesh.idx[3 * t], i1 = mesh.idx[3 * t + 1], i2 = mesh.idx[3 * t + 2];
             if (i0 >= mesh.V || i1 >= mesh.V || i2 >= mesh.V) continue;
             for (uint32_t d = d0; d < d1; ++d) {
-                const DrawDesc& D = a.draws[d];
-                const ViewDesc V = a.views[D.view];
+                const DrawDesc D = d_draws[d];
+                const ViewDesc V = d_views[D.view];
                 const Clip c[3] = {transform(D.A, mesh.pos[3 * (size_t)i0], mesh.pos[3 * (size_t)i0 + 1], mesh.pos[3 * (size_t)i0 + 2]),
                                    transform(D.A, mesh.pos[3 * (size_t)i1], mesh.pos[3 * (size_t)i1 + 1], mesh.pos[3 * (size_t)i1 + 2]),
                                    transform(D.A, mesh.pos[3 * (size_t)i2], mesh.pos[3 * (size_t)i2 + 1], mesh.pos[3 * (size_t)i2 + 2])};
@@ -476,8 +713,8 @@ hipError_t launch_clear(const RasterArgs& a, uint32_t grid, hipStream_t s)
 template <int BLOCK, int TPT>
 static hipError_t stage1_dispatch(const RasterArgs& a, bool stats, uint32_t grid, hipStream_t s)
 {
-    if (stats) stage1_kernel<BLOCK, TPT, true><<<grid, BLOCK, 0, s>>>(a);
-    else stage1_kernel<BLOCK, TPT, false><<<grid, BLOCK, 0, s>>>(a);
+    if (stats) stage1_kernel<BLOCK, TPT, true><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    else stage1_kernel<BLOCK, TPT, false><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
     return hipGetLastError();
 }
 
@@ -503,9 +740,39 @@ hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool
     }
 }
 
+template <int BLOCK, int TPT>
+static hipError_t stage1_fast_dispatch(const RasterArgs& a, bool stats, uint32_t grid, hipStream_t s)
+{
+    if (stats) stage1_fast_kernel<BLOCK, TPT, true><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    else stage1_fast_kernel<BLOCK, TPT, false><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    return hipGetLastError();
+}
+
+template <int BLOCK>
+static hipError_t stage1_fast_tpt(const RasterArgs& a, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s)
+{
+    switch (tpt) {
+    case 1: return stage1_fast_dispatch<BLOCK, 1>(a, stats, grid, s);
+    case 2: return stage1_fast_dispatch<BLOCK, 2>(a, stats, grid, s);
+    case 4: return stage1_fast_dispatch<BLOCK, 4>(a, stats, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s)
+{
+    switch (block) {
+    case 64: return stage1_fast_tpt<64>(a, tpt, stats, grid, s);
+    case 128: return stage1_fast_tpt<128>(a, tpt, stats, grid, s);
+    case 256: return stage1_fast_tpt<256>(a, tpt, stats, grid, s);
+    case 512: return stage1_fast_tpt<512>(a, tpt, stats, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_stage1_overflow(const RasterArgs& a, uint32_t grid, hipStream_t s)
 {
-    stage1_overflow_kernel<<<grid, 256, 0, s>>>(a);
+    stage1_overflow_kernel<<<grid, 256, 0, s>>>(a, CURAST_DESC_ARGS(a));
     return hipGetLastError();
 }
 

@@ -24,6 +24,7 @@
 namespace curast {
 hipError_t launch_clear(const RasterArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s);
+hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s);
 hipError_t launch_stage1_overflow(const RasterArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_stage2(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
 hipError_t launch_stage3(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
@@ -116,6 +117,7 @@ int validate_options(const curast_options& o, std::string& msg)
     if (o.s1_tris_per_thread && o.s1_tris_per_thread != 1 && o.s1_tris_per_thread != 2 && o.s1_tris_per_thread != 4)
         return bad("s1_tris_per_thread must be 1, 2 or 4");
     if (o.small_px > 65536) return bad("small_px must be <= 65536");
+    if (o.s1_mode > 3) return bad("s1_mode must be 0, 1, 2 or 3");
     if (o.s1_draws_per_item > 65536) return bad("s1_draws_per_item must be <= 65536");
     if (o.q2_capacity > (1u << 30) || o.q3_capacity > (1u << 30) || o.large_capacity > (1u << 28))
         return bad("queue capacity too large");
@@ -287,12 +289,13 @@ struct Plan {
     uint64_t draws_culled = 0;
     uint64_t total_pixels = 0;
     uint64_t max_batches = 0;        // without any culling (graph grid bound)
+    uint64_t pair_count = 0;
     size_t max_draws = 0;            // without any culling
     size_t off_views = 0, off_meshes = 0, off_segs = 0, off_draws = 0, bytes = 0, max_bytes = 0;
 };
 
-int build_plan(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* views, uint32_t n_views,
-               Plan& P)
+int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* meshes, uint32_t M,
+               const curast_view* views, uint32_t n_views, Plan& P, uint8_t* visible = nullptr)
 {
     if (M && !meshes) return fail(ctx, CURAST_E_INVALID, "meshes is NULL");
     if (!views || n_views == 0) return fail(ctx, CURAST_E_INVALID, "no view");
@@ -310,9 +313,8 @@ int build_plan(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const cur
         total_ids += meshes[m].num_triangles * (uint64_t)n_inst(meshes[m]);
         if (total_ids > kMaxIds) return fail(ctx, CURAST_E_ID_RANGE, "more than 2^36 triangle instances");
     }
-    const curast_options& o = ctx->opt;
     const bool cull = !(o.flags & kFlagNoMeshCull);
-    const uint32_t bt = o.s1_block * o.s1_tris_per_thread;
+    const uint32_t bt = o.s1_block * o.s1_tris_per_thread;   // triangles per stage-1 work item
     const uint32_t dpi = o.s1_draws_per_item;
     P.views.resize(n_views);
     for (uint32_t v = 0; v < n_views; ++v) {
@@ -339,11 +341,17 @@ int build_plan(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const cur
         const uint32_t ni = n_inst(me);
         const uint32_t draw_begin = (uint32_t)P.draws.size();
         for (uint32_t i = 0; i < ni; ++i, base += me.num_triangles) {
-            if (me.num_triangles == 0) continue;
+            if (me.num_triangles == 0) {
+                if (visible)
+                    for (uint32_t v = 0; v < n_views; ++v) visible[(P.pair_count + i) * (uint64_t)n_views + v] = 0;
+                continue;
+            }
             for (uint32_t v = 0; v < n_views; ++v) {
                 DrawDesc D;
                 draw_matrix(views[v].view_proj, me.instances ? me.instances + 12ull * i : nullptr, D.A);
-                if (cull && sphere_outside(D.A, me.bsphere, views[v].near_plane)) {
+                const bool out = cull && sphere_outside(D.A, me.bsphere, views[v].near_plane);
+                if (visible) visible[(P.pair_count + i) * (uint64_t)n_views + v] = out ? 0 : 1;
+                if (out) {
                     P.draws_culled++;
                     continue;
                 }
@@ -353,6 +361,7 @@ int build_plan(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const cur
                 P.draws.push_back(D);
             }
         }
+        P.pair_count += ni;
         const uint32_t dc = (uint32_t)P.draws.size() - draw_begin;
         const uint64_t tbatches = (me.num_triangles + bt - 1) / bt;
         if (me.num_triangles) {
@@ -416,6 +425,7 @@ RasterArgs make_args(curast_ctx* ctx, const Plan& P)
     a.small_px = ctx->opt.small_px;
     a.medium_px = ctx->opt.medium_px;
     a.flags = ctx->opt.flags;
+    a.s1_mode = ctx->opt.s1_mode;
     return a;
 }
 
@@ -442,7 +452,9 @@ int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, hipStream_t s, 
     e = launch_clear(a, clear_grid, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "clear kernel launch");
     if (tf) hipEventRecord(tf->ev[1], s);
-    e = launch_stage1(a, ctx->opt.s1_block, ctx->opt.s1_tris_per_thread, stats, std::max<uint32_t>(grid1, 1), s);
+    e = ctx->opt.s1_mode == 1
+            ? launch_stage1(a, ctx->opt.s1_block, ctx->opt.s1_tris_per_thread, stats, std::max<uint32_t>(grid1, 1), s)
+            : launch_stage1_fast(a, ctx->opt.s1_block, ctx->opt.s1_tris_per_thread, stats, std::max<uint32_t>(grid1, 1), s);
     if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 kernel launch");
     if (tf) hipEventRecord(tf->ev[2], s);
     e = launch_stage1_overflow(a, cus * 4, s);
@@ -468,7 +480,7 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
     if (!ctx) return CURAST_E_INVALID;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     Plan P;
-    int rc = build_plan(ctx, meshes, M, views, n_views, P);
+    int rc = build_plan(ctx, ctx->opt, meshes, M, views, n_views, P);
     if (rc) return rc;
     rc = ensure_queues(ctx);
     if (rc) return rc;
@@ -918,6 +930,30 @@ int curast_reset_stage_times(curast_ctx* ctx)
     collect_timings(ctx);
     for (int i = 0; i < kNumSlots; ++i) ctx->stage_ms[i] = 0.0;
     ctx->timed_frames = 0;
+    return CURAST_OK;
+}
+
+int curast_plan(const curast_mesh* meshes, uint32_t M, const curast_view* views, uint32_t n_views,
+                const curast_options* opt, uint8_t* visible, int64_t* bases, uint64_t counts[4])
+{
+    curast_options u{};
+    if (opt) u = *opt;
+    std::string msg;
+    if (validate_options(u, msg)) return CURAST_E_INVALID;
+    const curast_options o = resolve_defaults(u, 256);
+    Plan P;
+    int rc = build_plan(nullptr, o, meshes, M, views, n_views, P, visible);
+    if (rc) return rc;
+    if (bases) {
+        int64_t n = curast_id_bases(meshes, M, bases);
+        if (n < 0) return (int)n;
+    }
+    if (counts) {
+        counts[0] = P.draws.size();
+        counts[1] = P.draws_culled;
+        counts[2] = P.hdr.total_batches;
+        counts[3] = P.tri_draws;
+    }
     return CURAST_OK;
 }
 

@@ -282,15 +282,12 @@ def uv_sphere(lat: int, lon: int, radius=1.0):
 
 
 def bounding_sphere(pos: np.ndarray) -> np.ndarray:
-    """Centre of the axis-aligned box and the largest vertex distance, padded by a relative 1e-5."""
+    """Sphere around the axis-aligned bounding box (centre, half-diagonal), padded by a relative
+    1e-5: it contains every vertex."""
     lo = pos.min(axis=0).astype(np.float64)
     hi = pos.max(axis=0).astype(np.float64)
     c = 0.5 * (lo + hi)
-    r = 0.0
-    step = 1 << 24
-    for s in range(0, pos.shape[0], step):
-        d = pos[s:s + step].astype(np.float64) - c
-        r = max(r, float(np.sqrt((d * d).sum(axis=1).max())))
+    r = 0.5 * float(np.linalg.norm(hi - lo))
     r = r * (1.0 + 1e-5) + 1e-7
     return np.array([c[0], c[1], c[2], r], dtype=np.float32)
 
@@ -384,11 +381,17 @@ def scene_c1() -> Scene:
     return Scene("c1_sphere_ground_512", [sphere, ground], [view])
 
 
-def _hf_mesh(n, amplitude, seed, attr_seed=None) -> Mesh:
+def _hf_mesh(n, amplitude, seed, attr_seed=None, attr_normal=False) -> Mesh:
+    """Height field mesh with per-vertex RGB: uniform [0, 1) by default, N(0.5, 0.1) when
+    attr_normal (both drawn in float32 from numpy's default generator with attr_seed)."""
     pos, idx = heightfield(n, amplitude, seed)
     attrs = None
     if attr_seed is not None:
-        attrs = np.random.default_rng(attr_seed).normal(0.5, 0.1, (pos.shape[0], 3)).astype(np.float32)
+        rng = np.random.default_rng(attr_seed)
+        if attr_normal:
+            attrs = rng.standard_normal((pos.shape[0], 3), dtype=np.float32) * np.float32(0.1) + np.float32(0.5)
+        else:
+            attrs = rng.random((pos.shape[0], 3), dtype=np.float32)
     return Mesh(pos, idx, attrs=attrs, bsphere=bounding_sphere(pos))
 
 
@@ -468,7 +471,7 @@ def scene_c5(n: int = 2236) -> Scene:
     """Differentiable resolve: 2236^2 height field (seed 5, amplitude 0.1, T = 9,990,450),
     1024 x 1024 camera as C2, attributes RGB N(0.5, 0.1) (seed 55); the target image
     N(0.5, 0.1) per pixel (seed 56) is stored in meta['target']."""
-    hf = _hf_mesh(n, 0.1, 5, attr_seed=55)
+    hf = _hf_mesh(n, 0.1, 5, attr_seed=55, attr_normal=True)
     view = _hf_camera(1024, 1024)
     target = np.random.default_rng(56).normal(0.5, 0.1, (1024, 1024, 3)).astype(np.float32)
     return Scene(f"c5_heightfield_{n}_1024", [hf], [view], meta={"target": target})

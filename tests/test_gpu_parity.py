@@ -81,6 +81,11 @@ OPTION_SWEEP = [
     dict(flags=api.FLAG_NO_TINY_CULL | api.FLAG_NO_EARLY_OUT | api.FLAG_NO_MESH_CULL),
     dict(small_px=1, medium_px=1, s3_blocks=1, s2_waves=4), dict(q2_capacity=3, q3_capacity=5, large_capacity=2),
     dict(flags=api.FLAG_STATS | api.FLAG_TIMING),
+    dict(s1_mode=1), dict(s1_mode=2), dict(s1_mode=3), dict(s1_mode=3, s1_block=64),
+    dict(s1_mode=2, s1_block=512), dict(s1_mode=3, s1_block=128, s1_draws_per_item=2),
+    dict(s1_mode=3, flags=api.FLAG_NO_TINY_CULL), dict(s1_mode=2, flags=api.FLAG_ZERO_QUEUES),
+    dict(s1_mode=0, s1_tris_per_thread=2), dict(s1_mode=2, s1_tris_per_thread=4, s1_block=128),
+    dict(s1_mode=0, s1_tris_per_thread=4, s1_block=64, small_px=2),
 ]
 
 
@@ -96,6 +101,20 @@ def test_options_do_not_change_results(opts):
             t = W.random_tiny_scene(seed, near_crossing=True, spread=6.0, n_tris=24)
             v2 = c.rasterize_meshes(gpu_meshes(t), t.views[0])
             assert_vis_equal(api.as_uint64(v2), O.rasterize(t.meshes, t.views[0]), f"tiny {seed} with {opts}")
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2, 3])
+def test_instanced_stage1_modes(mode):
+    """Instanced meshes go through the vertex-sharing path (LDS deduplication) in modes 0 and 3."""
+    with api.Context(s1_mode=mode, s1_draws_per_item=8) as c:
+        for seed in range(6):
+            s = W.random_tiny_scene(seed, n_instances=13, n_tris=40, spread=3.0)
+            # shared vertices: rebuild the index buffer over a small vertex pool
+            rng = np.random.default_rng(seed)
+            m = s.meshes[0]
+            m.idx = rng.integers(0, 17, m.idx.shape).astype(np.uint32)
+            vis = c.rasterize_meshes(gpu_meshes(s), s.views[0])
+            assert_vis_equal(api.as_uint64(vis), O.rasterize(s.meshes, s.views[0]), f"instanced seed {seed} mode {mode}")
 
 
 def test_north_star_entry_point_matches_mesh_list(ctx):
