@@ -1,0 +1,136 @@
+"""GPU parity at the full sizes of the five workloads, in the launch configuration bench.py times.
+
+C2 and C3 compare the whole visibility buffer with the full oracle (C3: 9.1G triangle instances,
+about a minute of CPU time on 16 cores).  C4 checks the batched graph launch view by view against
+plain launches (every view) and the oracle (sampled views), over several graph replays.  C5
+checks the differentiable resolve: forward, fp64 reference gradients and central differences.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from helpers import assert_resolve_close, assert_vis_equal, oracle_threads
+from paper_2604_21749_amd import api
+from paper_2604_21749_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_meshes(scene):
+    return [api.GpuMesh.from_host(m) for m in scene.meshes]
+
+
+def test_c2_full_parity():
+    s = W.scene_c2()
+    view = s.views[0]
+    with api.Context() as c:
+        gm = gpu_meshes(s)
+        vis = c.rasterize_meshes(gm, view)
+        out = c.resolve(gm, view, vis, [m.attrs for m in gm])
+        got = api.as_uint64(vis)
+        got_out = out.cpu().numpy()
+    ref = O.rasterize(s.meshes, view, threads=oracle_threads())
+    assert_vis_equal(got, ref, "C2")
+    assert (ref != O.EMPTY).sum() > 400000
+    assert_resolve_close(got_out, O.resolve(s.meshes, view, ref, [m.attrs for m in s.meshes],
+                                            threads=oracle_threads()), "C2 resolve")
+
+
+@pytest.mark.timeout(900)
+def test_c3_full_parity():
+    s = W.scene_c3()
+    view = s.views[0]
+    with api.Context() as c:                      # default options: the benchmark's configuration
+        gm = gpu_meshes(s)
+        vis = c.rasterize_meshes(gm, view)
+        out = c.resolve(gm, view, vis, [m.attrs for m in gm])
+        got = api.as_uint64(vis)
+        got_out = out.cpu().numpy()
+        del gm, vis, out
+    torch.cuda.empty_cache()
+    print(f"[c3] GPU frame done, running the oracle on {oracle_threads()} threads", flush=True)
+    ref = O.rasterize(s.meshes, view, threads=oracle_threads())
+    assert_vis_equal(got, ref, "C3")
+    ids = O.key_id(ref[ref != O.EMPTY]).astype(np.int64)
+    assert (ids >= s.meshes[0].num_triangles).sum() > 1000      # instanced spheres are visible
+    assert_resolve_close(got_out, O.resolve(s.meshes, view, ref, [m.attrs for m in s.meshes],
+                                            threads=oracle_threads()), "C3 resolve")
+
+
+@pytest.mark.timeout(900)
+def test_c4_batched_graph_matches_plain_and_oracle():
+    s = W.scene_c4()
+    views = s.views
+    with api.Context() as c:
+        gm = gpu_meshes(s)
+        plain = [c.rasterize_meshes(gm, v) for v in views]
+        torch.cuda.synchronize()
+        plain_h = [api.as_uint64(p) for p in plain]
+        outs = [torch.empty_like(p) for p in plain]
+        rng = np.random.default_rng(7)
+        for replay in range(3):
+            for o in outs:
+                o.fill_(0)                        # eager work between replays
+            torch.cuda.synchronize()
+            c.rasterize_batched(gm, views, outs)
+            torch.cuda.synchronize()
+            for i, o in enumerate(outs):
+                assert_vis_equal(api.as_uint64(o), plain_h[i], f"C4 replay {replay} view {i}")
+        # a replay with different cameras (same structure): the graph is reused with new descriptors
+        moved = [W.orbit_camera((0.5, 0.0, 0.5), rng.uniform(0, 6.28), rng.uniform(0.4, 1.1), rng.uniform(0.4, 1.4),
+                                v.width, v.height) for v in views]
+        c.rasterize_batched(gm, moved, outs)
+        torch.cuda.synchronize()
+        for i in (0, 17, 63):
+            ref_plain = api.as_uint64(c.rasterize_meshes(gm, moved[i]))
+            assert_vis_equal(api.as_uint64(outs[i]), ref_plain, f"C4 moved view {i}")
+    for i in (0, 31):
+        ref = O.rasterize(s.meshes, views[i], threads=oracle_threads())
+        assert_vis_equal(plain_h[i], ref, f"C4 view {i} vs oracle")
+
+
+def test_c5_resolve_forward_and_backward():
+    s = W.scene_c5()
+    m = s.meshes[0]
+    view = s.views[0]
+    target = s.meta["target"]
+    with api.Context() as c:
+        g = api.GpuMesh.from_host(m)
+        vis = c.rasterize_meshes([g], view)
+        pos_ss = c.project(g, view)
+        out = c.resolve_screen(vis, g.idx, pos_ss, g.attrs)
+        torch.cuda.synchronize()
+        vis_h = api.as_uint64(vis)
+        pss_h = pos_ss.cpu().numpy()
+        # autograd wrapper: L = sum (out - target)^2 restricted to covered pixels
+        attrs = g.attrs.clone().requires_grad_(True)
+        pss = pos_ss.clone().requires_grad_(True)
+        img = api.ResolveFn.apply(attrs, pss, vis, g.idx, 0, c)
+        tgt = torch.from_numpy(target).cuda()
+        covered = (vis != -1).unsqueeze(-1)
+        loss = torch.where(covered, (img - tgt) ** 2, torch.zeros_like(img)).sum()
+        loss.backward()
+        ga = attrs.grad.cpu().numpy().astype(np.float64)
+        gp = pss.grad.cpu().numpy().astype(np.float64)
+        out_h = out.cpu().numpy()
+    ref_vis = O.rasterize([m], view, threads=oracle_threads())
+    assert_vis_equal(vis_h, ref_vis, "C5")
+    assert np.array_equal(pss_h, O.project(m, view)), "screen positions differ from the oracle"
+    assert_resolve_close(out_h, O.resolve_screen(ref_vis, m.idx, 0, pss_h, m.attrs), "C5 resolve")
+    # fp64 reference gradients with the same upstream gradient
+    out64 = O.resolve_screen_f64(ref_vis, m.idx, 0, pss_h, m.attrs)
+    cov = ref_vis != O.EMPTY
+    gout = np.where(cov[..., None], 2.0 * (out64 - target), 0.0)
+    ra, rp = O.resolve_screen_backward_f64(ref_vis, m.idx, 0, pss_h, m.attrs, gout)
+    sa = np.maximum(np.abs(ra), 1e-3 * np.sqrt(np.mean(ra ** 2)))
+    assert np.all(np.abs(ga - ra) <= 1e-3 * sa), f"attribute gradient: {np.max(np.abs(ga - ra) / sa)}"
+    sp = np.maximum(np.abs(rp), 1e-3 * np.sqrt(np.mean(rp ** 2)))
+    assert np.all(np.abs(gp - rp) <= 1e-3 * sp), f"position gradient: {np.max(np.abs(gp - rp) / sp)}"
+    # central finite differences (eps 1e-3, fourth-order stencil) on 256 seeded visible vertices
+    used = np.unique(m.idx[O.key_id(ref_vis[cov]).astype(np.int64)])
+    verts = np.random.default_rng(57).choice(used, 256, replace=False).astype(np.uint32)
+    fd = O.fd_pos_grad_l2(ref_vis, m.idx, 0, pss_h, m.attrs, target, verts, eps=1e-3, order4=True)
+    scale = np.maximum(np.abs(fd), 1e-3 * np.sqrt(np.mean(fd ** 2)))
+    rel = np.abs(gp[verts] - fd) / scale
+    assert np.all(rel <= 1e-3), f"FD check: worst relative error {rel.max()}"
