@@ -243,7 +243,8 @@ int curast_reset_stage_times(curast_ctx* ctx);
 /*
  * Host-side frame planning only (no GPU; Sec. 4 host mesh list): validates the arguments as the
  * rasterize calls do and reports which (mesh, instance, view) draws survive the conservative
- * bounding-sphere frustum cull.  visible: host [pairs][n_views] bytes (1 = drawn) or NULL;
+ * bounding-sphere frustum cull.  visible: host [pairs][n_views] bytes (0 = culled, 1 = drawn,
+ * 2 = drawn and proven to lie in front of the near plane inside |x|, |y| <= 1.99 w) or NULL;
  * bases: host [pairs + 1] exclusive prefix of triangle counts or NULL; counts: host [4] = draws
  * kept, draws culled, stage-1 work items, triangle x draw items, or NULL.  Views' visbuffer
  * pointers must be non-NULL but are not touched.

@@ -416,7 +416,8 @@ def id_bases(meshes: Sequence[GpuMesh]) -> np.ndarray:
 
 
 def plan(meshes: Sequence[GpuMesh], views, **options):
-    """curast_plan (host only): (visible [pairs, n_views] bool, bases [pairs + 1], counts dict)."""
+    """curast_plan (host only): (visible [pairs, n_views] uint8: 0 culled, 1 drawn, 2 drawn and
+    interior; bases [pairs + 1]; counts dict)."""
     keep = []
     arr = (MeshStruct * max(1, len(meshes)))(*[_mesh_struct(m, keep, check=False) for m in meshes])
     dummy = (C.c_uint64 * max(1, len(views)))()     # distinct non-NULL buffers, never touched
@@ -433,7 +434,7 @@ def plan(meshes: Sequence[GpuMesh], views, **options):
                            counts.ctypes.data)
     if rc != OK:
         raise CurastError(rc, lib().curast_status_string(rc).decode())
-    return visible.astype(bool), bases, dict(zip(("draws", "culled", "work_items", "tri_draws"), map(int, counts)))
+    return visible, bases, dict(zip(("draws", "culled", "work_items", "tri_draws"), map(int, counts)))
 
 
 class ResolveFn(torch.autograd.Function):

@@ -60,12 +60,17 @@ struct Segment {                  // 32 B
 };
 
 // One (mesh, instance, view): rows x, y, w of VP * X, the global ID of triangle 0, the view.
+// Bit 31 of `view` (kDrawInterior) marks draws whose bounding sphere the host proved to lie in
+// front of the near plane and inside |x|, |y| <= 1.99 w: no vertex of such a draw needs the
+// per-vertex near/guard tests of the fast stage-1 path.
 struct DrawDesc {                 // 64 B
     float A[12];
     uint64_t id_base;
     uint32_t view;
     uint32_t mesh;
 };
+constexpr uint32_t kDrawInterior = 0x80000000u;
+constexpr uint32_t kDrawViewMask = 0x7FFFFFFFu;
 
 struct Q2Entry {                  // triangle forwarded by stage 1
     uint32_t draw;

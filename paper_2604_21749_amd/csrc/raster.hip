@@ -302,7 +302,7 @@ __global__ void __launch_bounds__(BLOCK) stage1_kernel(RasterArgs a, CURAST_DESC
 #pragma unroll 1
             for (uint32_t d = d0; d < d1; ++d) {
                 const DrawDesc D = d_draws[d];
-                const ViewDesc V = d_views[D.view];
+                const ViewDesc V = d_views[D.view & kDrawViewMask];
                 int route = kRouteNone;
                 SmallTri s;
                 if (valid) {
@@ -364,6 +364,13 @@ __device__ __forceinline__ float2 fast_window(const Clip& c, const ViewDesc& V)
     return make_float2(__builtin_fmaf(c.x * r, V.hW, V.hW), __builtin_fmaf(c.y * r, V.hH, V.hH));
 }
 
+// Same for a vertex of an interior draw (range tests proven on the host).
+__device__ __forceinline__ float2 fast_window_interior(const Clip& c, const ViewDesc& V)
+{
+    const float r = __builtin_amdgcn_rcpf(c.w);
+    return make_float2(__builtin_fmaf(c.x * r, V.hW, V.hW), __builtin_fmaf(c.y * r, V.hH, V.hH));
+}
+
 // True when the triangle provably covers no pixel centre of the view.
 __device__ __forceinline__ bool fast_reject(float2 a, float2 b, float2 c, const ViewDesc& V, bool tiny_cull)
 {
@@ -415,7 +422,7 @@ __device__ __forceinline__ void drain_ring(const RasterArgs& a, const ViewDesc* 
         tt = e.tri;
         const Clip c[3] = {{e.c[0], e.c[1], e.c[2]}, {e.c[3], e.c[4], e.c[5]}, {e.c[6], e.c[7], e.c[8]}};
         const DrawDesc& D = d_draws[dd];
-        V = d_views[D.view];
+        V = d_views[D.view & kDrawViewMask];
         idb = D.id_base;
         route = classify<STATS>(c, V, a.small_px, tiny_cull, s, st);
     }
@@ -486,7 +493,8 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
 #pragma unroll 1
         for (uint32_t d = d0; d < d1; ++d) {
             const DrawDesc D = d_draws[d];
-            const ViewDesc V = d_views[D.view];
+            const ViewDesc V = d_views[D.view & kDrawViewMask];
+            const bool interior = (D.view & kDrawInterior) != 0;
 #pragma unroll
             for (int k = 0; k < TPT; ++k) {
                 const Clip c0 = transform(D.A, p[k][0], p[k][1], p[k][2]);
@@ -495,7 +503,11 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                 bool need = false;
                 if (valid[k]) {
                     st.add(kStTriDraws);
-                    need = !fast_reject(fast_window(c0, V), fast_window(c1, V), fast_window(c2, V), V, tiny_cull);
+                    if (interior)
+                        need = !fast_reject(fast_window_interior(c0, V), fast_window_interior(c1, V),
+                                            fast_window_interior(c2, V), V, tiny_cull);
+                    else
+                        need = !fast_reject(fast_window(c0, V), fast_window(c1, V), fast_window(c2, V), V, tiny_cull);
                     if (!need) st.add(kStCulledTiny);
                 }
                 const unsigned long long m = __ballot(need);
@@ -553,7 +565,7 @@ __global__ void __launch_bounds__(256) stage1_overflow_kernel(RasterArgs a, CURA
             if (i0 >= mesh.V || i1 >= mesh.V || i2 >= mesh.V) continue;
             for (uint32_t d = d0; d < d1; ++d) {
                 const DrawDesc D = d_draws[d];
-                const ViewDesc V = d_views[D.view];
+                const ViewDesc V = d_views[D.view & kDrawViewMask];
                 const Clip c[3] = {transform(D.A, mesh.pos[3 * (size_t)i0], mesh.pos[3 * (size_t)i0 + 1], mesh.pos[3 * (size_t)i0 + 2]),
                                    transform(D.A, mesh.pos[3 * (size_t)i1], mesh.pos[3 * (size_t)i1 + 1], mesh.pos[3 * (size_t)i1 + 2]),
                                    transform(D.A, mesh.pos[3 * (size_t)i2], mesh.pos[3 * (size_t)i2 + 1], mesh.pos[3 * (size_t)i2 + 2])};
@@ -582,7 +594,7 @@ __global__ void __launch_bounds__(256) stage2_kernel(RasterArgs a)
         const uint32_t d = __builtin_amdgcn_readfirstlane(q.draw);
         const uint32_t t = __builtin_amdgcn_readfirstlane(q.tri);
         const DrawDesc& D = a.draws[d];
-        const ViewDesc V = a.views[D.view];
+        const ViewDesc V = a.views[D.view & kDrawViewMask];
         const MeshDesc M = a.meshes[D.mesh];
         const uint64_t id = D.id_base + t;
         Clip c[3];
@@ -632,7 +644,7 @@ __global__ void __launch_bounds__(256) stage2_kernel(RasterArgs a)
                             r.Y[k] = ty[k];
                             r.zI[k] = tz[k];
                         }
-                        r.view = D.view;
+                        r.view = D.view & kDrawViewMask;
                         r.id = id;
                         a.large[rec] = r;
                     }

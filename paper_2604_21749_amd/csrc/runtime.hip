@@ -253,6 +253,47 @@ bool sphere_outside(const float A[12], const float bs[4], float near_plane)
     return test(pl);
 }
 
+// True when every point of the bounding sphere satisfies w >= near (with slack), w < 1e29 and
+// |x|, |y| <= 1.99 w: the fast stage-1 path may then skip its per-vertex range tests.  The slack
+// (relative 1e-3 and the 1.99 factor) dwarfs the binary32 error of the kernel's transform.
+bool sphere_interior(const float A[12], const float bs[4], float near_plane)
+{
+    if (!(bs[3] > 0.0f)) return false;
+    const double c[4] = {bs[0], bs[1], bs[2], 1.0};
+    const double r = bs[3];
+    auto range = [&](const double* pl, double& lo, double& hi) {
+        double v = 0.0, mag = 0.0;
+        for (int k = 0; k < 4; ++k) {
+            v += pl[k] * c[k];
+            mag += std::fabs(pl[k] * c[k]);
+        }
+        const double g = std::sqrt(pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2]);
+        const double slack = 1e-4 * (mag + r * g);
+        lo = v - r * g - slack;
+        hi = v + r * g + slack;
+    };
+    double x[4], y[4], w[4], pl[4], lo, hi;
+    for (int k = 0; k < 4; ++k) {
+        x[k] = A[k];
+        y[k] = A[4 + k];
+        w[k] = A[8 + k];
+    }
+    range(w, lo, hi);
+    if (!(lo >= 1.001 * (double)near_plane) || !(hi < 1e29)) return false;
+    for (int k = 0; k < 4; ++k) pl[k] = 1.99 * w[k] - x[k];
+    range(pl, lo, hi);
+    if (!(lo > 0.0)) return false;
+    for (int k = 0; k < 4; ++k) pl[k] = 1.99 * w[k] + x[k];
+    range(pl, lo, hi);
+    if (!(lo > 0.0)) return false;
+    for (int k = 0; k < 4; ++k) pl[k] = 1.99 * w[k] - y[k];
+    range(pl, lo, hi);
+    if (!(lo > 0.0)) return false;
+    for (int k = 0; k < 4; ++k) pl[k] = 1.99 * w[k] + y[k];
+    range(pl, lo, hi);
+    return lo > 0.0;
+}
+
 int check_view(curast_ctx* ctx, const curast_view& v, bool need_vis = true)
 {
     if (v.width < 1 || v.height < 1 || v.width > kMaxDim || v.height > kMaxDim)
@@ -350,13 +391,14 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
                 DrawDesc D;
                 draw_matrix(views[v].view_proj, me.instances ? me.instances + 12ull * i : nullptr, D.A);
                 const bool out = cull && sphere_outside(D.A, me.bsphere, views[v].near_plane);
-                if (visible) visible[(P.pair_count + i) * (uint64_t)n_views + v] = out ? 0 : 1;
+                const bool inner = !out && sphere_interior(D.A, me.bsphere, views[v].near_plane);
+                if (visible) visible[(P.pair_count + i) * (uint64_t)n_views + v] = out ? 0 : inner ? 2 : 1;
                 if (out) {
                     P.draws_culled++;
                     continue;
                 }
                 D.id_base = base;
-                D.view = v;
+                D.view = v | (inner ? kDrawInterior : 0u);
                 D.mesh = m;
                 P.draws.push_back(D);
             }
