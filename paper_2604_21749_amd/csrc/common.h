@@ -26,9 +26,9 @@ struct FrameHeader {              // 32 B
     uint64_t total_batches;       // stage-1 work items over all segments
     uint32_t n_segs;
     uint32_t n_views;
-    uint32_t batch_tris;          // triangles per work item (block size * triangles per thread)
+    uint32_t batch_tris;          // triangles per work item of the plain stage-1 kernels
     uint32_t draws_per_item;      // draws per work item
-    uint64_t pad;
+    uint64_t shared_batches;      // work items [0, shared_batches) run the vertex-sharing kernel
 };
 
 struct ViewDesc {                 // 32 B
@@ -56,7 +56,8 @@ struct Segment {                  // 32 B
     uint32_t draw_begin;          // first draw of the mesh
     uint32_t draw_count;          // draws of the mesh that survived the host cull
     uint32_t n_groups;            // ceil(draw_count / draws_per_item)
-    uint64_t pad;
+    uint32_t batch_tris;          // triangles per work item of this segment
+    uint32_t pad;
 };
 
 // One (mesh, instance, view): rows x, y, w of VP * X, the global ID of triangle 0, the view.
@@ -125,6 +126,7 @@ struct RasterArgs {
     uint32_t small_px, medium_px;
     uint32_t flags;
     uint32_t s1_mode;             // 0 auto, 1 exact only, 2 fast reject, 3 fast reject + vertex sharing
+    uint32_t part;                // stage-1 work items: 0 all, 1 the shared prefix, 2 the rest
 };
 
 struct ResolveArgs {

@@ -221,6 +221,7 @@ struct WorkItem {
     uint32_t mesh;
     uint64_t tri_batch;
     uint32_t d0, d1;
+    uint32_t batch_tris;
 };
 
 __device__ __forceinline__ WorkItem locate_work(const Segment* __restrict__ segs, uint32_t n_segs, uint32_t dpi, uint64_t b);
@@ -236,6 +237,13 @@ __device__ __forceinline__ uint32_t find_segment(const Segment* __restrict__ seg
     return lo;
 }
 
+// Range of stage-1 work items a launch covers (see RasterArgs::part).
+__device__ __forceinline__ void work_range(const FrameHeader& h, uint32_t part, uint64_t& begin, uint64_t& end)
+{
+    begin = part == 2 ? uni64(h.shared_batches) : 0;
+    end = part == 1 ? uni64(h.shared_batches) : uni64(h.total_batches);
+}
+
 // Work item b -> (mesh, triangle batch, draw range), all uniform.
 __device__ __forceinline__ WorkItem locate_work(const Segment* __restrict__ segs, uint32_t n_segs, uint32_t dpi, uint64_t b)
 {
@@ -248,6 +256,7 @@ __device__ __forceinline__ WorkItem locate_work(const Segment* __restrict__ segs
     const uint64_t j = b - begin;
     WorkItem w;
     w.mesh = uni(sg.mesh);
+    w.batch_tris = uni(sg.batch_tris);
     uint32_t g = 0;
     if (ng == 1) {
         w.tri_batch = j;
@@ -270,13 +279,14 @@ template <int BLOCK, int TPT, bool STATS>
 __global__ void __launch_bounds__(BLOCK) stage1_kernel(RasterArgs a, CURAST_DESC_PARAMS)
 {
     const FrameHeader hdr = *d_hdr;
-    const uint64_t total = uni64(hdr.total_batches);
+    uint64_t first, total;
+    work_range(hdr, a.part, first, total);
     const uint32_t n_segs = uni(hdr.n_segs);
     const uint32_t dpi = uni(hdr.draws_per_item);
     const bool early_out = !(a.flags & kFlagNoEarlyOut);
     const bool tiny_cull = !(a.flags & kFlagNoTinyCull);
     StatAcc<STATS> st;
-    for (uint64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    for (uint64_t b = first + blockIdx.x; b < total; b += gridDim.x) {
         const WorkItem wi = locate_work(d_segs, n_segs, dpi, b);
         const uint64_t tb = wi.tri_batch;
         const uint32_t d0 = wi.d0, d1 = wi.d1;
@@ -450,7 +460,8 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
     constexpr int WAVES = BLOCK / 64;
     __shared__ RingEntry s_ring[WAVES][kRing];
     const FrameHeader hdr = *d_hdr;
-    const uint64_t total = uni64(hdr.total_batches);
+    uint64_t first, total;
+    work_range(hdr, a.part, first, total);
     const uint32_t n_segs = uni(hdr.n_segs);
     const uint32_t dpi = uni(hdr.draws_per_item);
     const bool early_out = !(a.flags & kFlagNoEarlyOut);
@@ -459,7 +470,7 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
     const uint32_t lane = lane_id();
     uint32_t head = 0, tail = 0;   // wave-uniform
     StatAcc<STATS> st;
-    for (uint64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    for (uint64_t b = first + blockIdx.x; b < total; b += gridDim.x) {
         const WorkItem wi = locate_work(d_segs, n_segs, dpi, b);
         const uint64_t tb = wi.tri_batch;
         const uint32_t d0 = wi.d0, d1 = wi.d1;
@@ -539,6 +550,205 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
     st.flush(a.stats);
 }
 
+// ----------------------------------------------------------------------------------------------
+// Stage 1 with vertex sharing, for triangles drawn many times (instances x views).  One wavefront
+// per workgroup: it deduplicates the vertex indices of its 64*TPT triangles in an LDS hash table
+// once per work item, then for every draw transforms each unique vertex once (window positions in
+// LDS) and tests each triangle from those.  The arithmetic of the fast test is the same as in
+// stage1_fast_kernel; undecided (triangle, draw) pairs go through the exact path after reloading
+// the triangle (rare for dense meshes).  Vertex reuse through shared memory is named as future
+// work in the paper's conclusion.
+// ----------------------------------------------------------------------------------------------
+struct IdEntry {
+    uint32_t draw;
+    uint32_t tri;
+};
+
+template <bool STATS>
+__device__ __forceinline__ void drain_ids(const RasterArgs& a, const ViewDesc* __restrict__ d_views,
+                                          const MeshDesc* __restrict__ d_meshes, const DrawDesc* __restrict__ d_draws,
+                                          const IdEntry* ring, uint32_t head, uint32_t n, bool tiny_cull,
+                                          bool early_out, StatAcc<STATS>& st)
+{
+    const uint32_t lane = lane_id();
+    int route = kRouteNone;
+    SmallTri s;
+    uint32_t dd = 0, tt = 0;
+    ViewDesc V;
+    uint64_t idb = 0;
+    if (lane < n) {
+        const IdEntry e = ring[(head + lane) & (kRing - 1)];
+        dd = e.draw;
+        tt = e.tri;
+        const DrawDesc& D = d_draws[dd];
+        V = d_views[D.view & kDrawViewMask];
+        idb = D.id_base;
+        const MeshDesc& M = d_meshes[D.mesh];
+        const CURAST_GLOBAL uint32_t* ip = gl(M.idx) + 3 * (uint64_t)tt;
+        Clip c[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const CURAST_GLOBAL float* q = gl(M.pos) + 3 * (size_t)ip[k];
+            c[k] = transform(D.A, q[0], q[1], q[2]);
+        }
+        route = classify<STATS>(c, V, a.small_px, tiny_cull, s, st);
+    }
+    const unsigned long long slot = wave_reserve(route == kRouteForward, a.counters + kCntQ2);
+    if (route == kRouteForward) {
+        st.add(kStQ2);
+        if (slot < a.q2_cap) {
+            Q2Entry qe;
+            qe.draw = dd;
+            qe.tri = tt;
+            a.q2[slot] = qe;
+        } else {
+            st.add(kStQ2Overflow);
+        }
+    }
+    if (route == kRouteSmall) {
+        st.add(kStS1Raster);
+        raster_small<STATS>(s, idb + tt, V, early_out, st);
+    }
+}
+
+__device__ __forceinline__ uint32_t vertex_hash(uint32_t v, int bits) { return (v * 2654435761u) >> (32 - bits); }
+
+template <int TPT, bool STATS>
+__global__ void __launch_bounds__(64) stage1_share_kernel(RasterArgs a, CURAST_DESC_PARAMS)
+{
+    constexpr int NT = 64 * TPT;                       // triangles per work item
+    constexpr int NI = 3 * NT;                         // vertex references
+    constexpr int RS = 3 * TPT;                        // rounds of 64 unique vertices at most
+    constexpr int HBITS = TPT == 1 ? 8 : TPT == 2 ? 9 : 10;
+    constexpr int HT = 1 << HBITS;                     // load factor <= 3/4
+    constexpr uint32_t kFree = 0xFFFFFFFFu;
+    __shared__ uint32_t s_key[HT];
+    __shared__ uint16_t s_val[HT];
+    __shared__ uint32_t s_uniq[NI];
+    __shared__ float2 s_win[NI];
+    __shared__ IdEntry s_ring[kRing];
+    __shared__ uint32_t s_nu;
+    const FrameHeader hdr = *d_hdr;
+    uint64_t first, total;
+    work_range(hdr, a.part, first, total);
+    const uint32_t n_segs = uni(hdr.n_segs);
+    const uint32_t dpi = uni(hdr.draws_per_item);
+    const bool early_out = !(a.flags & kFlagNoEarlyOut);
+    const bool tiny_cull = !(a.flags & kFlagNoTinyCull);
+    const uint32_t lane = threadIdx.x;
+    uint32_t head = 0, tail = 0;
+    StatAcc<STATS> st;
+    for (uint64_t b = first + blockIdx.x; b < total; b += gridDim.x) {
+        const WorkItem wi = locate_work(d_segs, n_segs, dpi, b);
+        const uint64_t tb = wi.tri_batch;
+        const uint32_t d0 = wi.d0, d1 = wi.d1;
+        const MeshDesc mesh = d_meshes[wi.mesh];
+        uint32_t vi[TPT][3], dv[TPT][3], tri[TPT];
+        bool valid[TPT];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            const uint64_t t = tb * (uint64_t)NT + (uint64_t)(k * 64) + lane;
+            tri[k] = (uint32_t)t;
+            valid[k] = t < mesh.T;
+            const CURAST_GLOBAL uint32_t* ip = gl(mesh.idx) + 3 * (valid[k] ? t : 0);
+            vi[k][0] = ip[0];
+            vi[k][1] = ip[1];
+            vi[k][2] = ip[2];
+        }
+        for (int i = lane; i < HT; i += 64) s_key[i] = kFree;
+        if (lane == 0) s_nu = 0;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            valid[k] = valid[k] && vi[k][0] < mesh.V && vi[k][1] < mesh.V && vi[k][2] < mesh.V;
+            if (!valid[k]) continue;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                uint32_t h = vertex_hash(vi[k][v], HBITS);
+                while (true) {
+                    const uint32_t prev = atomicCAS(&s_key[h], kFree, vi[k][v]);
+                    if (prev == kFree) {
+                        const uint32_t dn = atomicAdd(&s_nu, 1u);
+                        s_val[h] = (uint16_t)dn;
+                        s_uniq[dn] = vi[k][v];
+                        break;
+                    }
+                    if (prev == vi[k][v]) break;
+                    h = (h + 1) & (HT - 1);
+                }
+            }
+        }
+        __syncthreads();
+        const uint32_t nu = uni(s_nu);
+#pragma unroll
+        for (int k = 0; k < TPT; ++k)
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                dv[k][v] = 0;
+                if (valid[k]) {
+                    uint32_t h = vertex_hash(vi[k][v], HBITS);
+                    while (s_key[h] != vi[k][v]) h = (h + 1) & (HT - 1);
+                    dv[k][v] = s_val[h];
+                }
+            }
+        float pu[RS][3];
+#pragma unroll
+        for (int r = 0; r < RS; ++r) {
+            const uint32_t u = lane + 64 * r;
+            const CURAST_GLOBAL float* q = gl(mesh.pos) + 3 * (size_t)(u < nu ? s_uniq[u] : 0u);
+            pu[r][0] = q[0];
+            pu[r][1] = q[1];
+            pu[r][2] = q[2];
+        }
+#pragma unroll 1
+        for (uint32_t d = d0; d < d1; ++d) {
+            const DrawDesc D = d_draws[d];
+            const ViewDesc V = d_views[D.view & kDrawViewMask];
+            const bool interior = (D.view & kDrawInterior) != 0;
+#pragma unroll
+            for (int r = 0; r < RS; ++r) {
+                if (64 * r >= (int)nu) break;                // uniform
+                const uint32_t u = lane + 64 * r;
+                const Clip c = transform(D.A, pu[r][0], pu[r][1], pu[r][2]);
+                const float2 w = interior ? fast_window_interior(c, V) : fast_window(c, V);
+                if (u < nu) s_win[u] = w;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+                bool need = false;
+                if (valid[k]) {
+                    st.add(kStTriDraws);
+                    need = !fast_reject(s_win[dv[k][0]], s_win[dv[k][1]], s_win[dv[k][2]], V, tiny_cull);
+                    if (!need) st.add(kStCulledTiny);
+                }
+                const unsigned long long m = __ballot(need);
+                if (m) {
+                    if (need) {
+                        IdEntry e;
+                        e.draw = d;
+                        e.tri = tri[k];
+                        s_ring[(tail + rank_in(m)) & (kRing - 1)] = e;
+                    }
+                    tail += (uint32_t)__popcll(m);
+                    if (tail - head >= 64) {
+                        __syncthreads();
+                        drain_ids<STATS>(a, d_views, d_meshes, d_draws, s_ring, head, 64, tiny_cull, early_out, st);
+                        head += 64;
+                        __syncthreads();
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    if (tail != head) {
+        __syncthreads();
+        drain_ids<STATS>(a, d_views, d_meshes, d_draws, s_ring, head, tail - head, tiny_cull, early_out, st);
+    }
+    st.flush(a.stats);
+}
+
 // Stage-1 overflow pass: when more triangles were forwarded than Q2 holds, every forwarded
 // triangle is rasterized here by one thread (those that did fit are drawn twice; the minimum is
 // idempotent).  Exits at once when nothing overflowed.
@@ -546,18 +756,20 @@ __global__ void __launch_bounds__(256) stage1_overflow_kernel(RasterArgs a, CURA
 {
     if (a.counters[kCntQ2] <= a.q2_cap) return;
     const FrameHeader hdr = *d_hdr;
-    const uint64_t total = uni64(hdr.total_batches);
+    uint64_t first, total;
+    work_range(hdr, a.part, first, total);
     const uint32_t n_segs = uni(hdr.n_segs);
     const uint32_t dpi = uni(hdr.draws_per_item);
-    const uint32_t bt = uni(hdr.batch_tris);
+
     const bool early_out = !(a.flags & kFlagNoEarlyOut);
     const bool tiny_cull = !(a.flags & kFlagNoTinyCull);
     StatAcc<false> st;
-    for (uint64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    for (uint64_t b = first + blockIdx.x; b < total; b += gridDim.x) {
         const WorkItem wi = locate_work(d_segs, n_segs, dpi, b);
         const uint64_t tb = wi.tri_batch;
         const uint32_t d0 = wi.d0, d1 = wi.d1;
         const MeshDesc mesh = d_meshes[wi.mesh];
+        const uint32_t bt = wi.batch_tris;
         for (uint32_t tt = threadIdx.x; tt < bt; tt += blockDim.x) {
             const uint64_t t = tb * bt + tt;
             if (t >= mesh.T) break;
@@ -778,6 +990,24 @@ hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt,
     case 128: return stage1_fast_tpt<128>(a, tpt, stats, grid, s);
     case 256: return stage1_fast_tpt<256>(a, tpt, stats, grid, s);
     case 512: return stage1_fast_tpt<512>(a, tpt, stats, grid, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <int TPT>
+static hipError_t stage1_share_dispatch(const RasterArgs& a, bool stats, uint32_t grid, hipStream_t s)
+{
+    if (stats) stage1_share_kernel<TPT, true><<<grid, 64, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    else stage1_share_kernel<TPT, false><<<grid, 64, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    return hipGetLastError();
+}
+
+hipError_t launch_stage1_share(const RasterArgs& a, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s)
+{
+    switch (tpt) {
+    case 1: return stage1_share_dispatch<1>(a, stats, grid, s);
+    case 2: return stage1_share_dispatch<2>(a, stats, grid, s);
+    case 4: return stage1_share_dispatch<4>(a, stats, grid, s);
     default: return hipErrorInvalidValue;
     }
 }

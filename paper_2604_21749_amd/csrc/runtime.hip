@@ -25,6 +25,7 @@ namespace curast {
 hipError_t launch_clear(const RasterArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s);
 hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s);
+hipError_t launch_stage1_share(const RasterArgs& a, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s);
 hipError_t launch_stage1_overflow(const RasterArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_stage2(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
 hipError_t launch_stage3(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
@@ -371,6 +372,8 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
     }
     P.meshes.resize(M);
     uint64_t base = 0;
+    const uint32_t bt_share = 64u * o.s1_tris_per_thread;
+    std::vector<uint32_t> mesh_draw_begin(M), mesh_draw_count(M);
     for (uint32_t m = 0; m < M; ++m) {
         const curast_mesh& me = meshes[m];
         MeshDesc& md = P.meshes[m];
@@ -404,24 +407,37 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
             }
         }
         P.pair_count += ni;
-        const uint32_t dc = (uint32_t)P.draws.size() - draw_begin;
-        const uint64_t tbatches = (me.num_triangles + bt - 1) / bt;
+        mesh_draw_begin[m] = draw_begin;
+        mesh_draw_count[m] = (uint32_t)P.draws.size() - draw_begin;
         if (me.num_triangles) {
             const uint64_t all = (uint64_t)ni * n_views;
+            const uint64_t groups = (all + dpi - 1) / dpi;
             P.max_draws += all;
-            P.max_batches += tbatches * ((all + dpi - 1) / dpi);
+            P.max_batches += ((me.num_triangles + std::min(bt, bt_share) - 1) / std::min(bt, bt_share)) * groups;
         }
-        if (dc && me.num_triangles) {
-            Segment s{};
-            s.batch_begin = P.hdr.total_batches;
-            s.mesh = m;
-            s.draw_begin = draw_begin;
-            s.draw_count = dc;
-            s.n_groups = (dc + dpi - 1) / dpi;
-            P.segs.push_back(s);
-            P.hdr.total_batches += tbatches * s.n_groups;
-            P.tri_draws += me.num_triangles * (uint64_t)dc;
+    }
+    // stage-1 segments: meshes drawn several times first (vertex-sharing kernel), then the rest
+    auto shared_mesh = [&](uint32_t m) {
+        if (o.s1_mode == 3) return true;
+        if (o.s1_mode != 0) return false;
+        return mesh_draw_count[m] >= 4;
+    };
+    for (int pass = 0; pass < 2; ++pass) {
+        for (uint32_t m = 0; m < M; ++m) {
+            const uint32_t dc = mesh_draw_count[m];
+            if (!dc || !meshes[m].num_triangles || shared_mesh(m) != (pass == 0)) continue;
+            Segment sg{};
+            sg.batch_begin = P.hdr.total_batches;
+            sg.mesh = m;
+            sg.draw_begin = mesh_draw_begin[m];
+            sg.draw_count = dc;
+            sg.n_groups = (dc + dpi - 1) / dpi;
+            sg.batch_tris = pass == 0 ? bt_share : bt;
+            P.segs.push_back(sg);
+            P.hdr.total_batches += ((meshes[m].num_triangles + sg.batch_tris - 1) / sg.batch_tris) * sg.n_groups;
+            P.tri_draws += meshes[m].num_triangles * (uint64_t)dc;
         }
+        if (pass == 0) P.hdr.shared_batches = P.hdr.total_batches;
     }
     P.hdr.n_segs = (uint32_t)P.segs.size();
     P.hdr.n_views = n_views;
@@ -468,6 +484,7 @@ RasterArgs make_args(curast_ctx* ctx, const Plan& P)
     a.medium_px = ctx->opt.medium_px;
     a.flags = ctx->opt.flags;
     a.s1_mode = ctx->opt.s1_mode;
+    a.part = 0;
     return a;
 }
 
@@ -482,7 +499,7 @@ TimedFrame* begin_timing(curast_ctx* ctx)
 }
 
 // Launch the device part of a frame: clear, stage 1, overflow pass, stage 2, stage 3.
-int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, hipStream_t s, TimedFrame* tf)
+int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, uint32_t grid_share, hipStream_t s, TimedFrame* tf)
 {
     const RasterArgs a = make_args(ctx, P);
     const bool stats = ctx->opt.flags & kFlagStats;
@@ -494,10 +511,20 @@ int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, hipStream_t s, 
     e = launch_clear(a, clear_grid, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "clear kernel launch");
     if (tf) hipEventRecord(tf->ev[1], s);
-    e = ctx->opt.s1_mode == 1
-            ? launch_stage1(a, ctx->opt.s1_block, ctx->opt.s1_tris_per_thread, stats, std::max<uint32_t>(grid1, 1), s)
-            : launch_stage1_fast(a, ctx->opt.s1_block, ctx->opt.s1_tris_per_thread, stats, std::max<uint32_t>(grid1, 1), s);
-    if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 kernel launch");
+    {
+        // work items [0, shared) run the vertex-sharing kernel, the rest the plain one
+        RasterArgs a1 = a;
+        a1.part = 1;
+        if (grid_share) {
+            e = launch_stage1_share(a1, ctx->opt.s1_tris_per_thread, stats, grid_share, s);
+            if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 sharing kernel launch");
+        }
+        a1.part = 2;
+        e = ctx->opt.s1_mode == 1
+                ? launch_stage1(a1, ctx->opt.s1_block, ctx->opt.s1_tris_per_thread, stats, std::max<uint32_t>(grid1, 1), s)
+                : launch_stage1_fast(a1, ctx->opt.s1_block, ctx->opt.s1_tris_per_thread, stats, std::max<uint32_t>(grid1, 1), s);
+        if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 kernel launch");
+    }
     if (tf) hipEventRecord(tf->ev[2], s);
     e = launch_stage1_overflow(a, cus * 4, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 overflow kernel launch");
@@ -536,7 +563,8 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
         HIP_TRY(ctx, hipMemcpyAsync(ctx->raster_stage.dev, ctx->raster_stage.host, P.bytes, hipMemcpyHostToDevice, s));
         HIP_TRY(ctx, hipEventRecord(ctx->raster_stage.ev, s));
         ctx->raster_stage.pending = true;
-        rc = launch_frame(ctx, P, grid_for(P.hdr.total_batches), s, tf);
+        const uint64_t shared = P.hdr.shared_batches;
+        rc = launch_frame(ctx, P, grid_for(P.hdr.total_batches - shared), shared ? grid_for(shared) : 0, s, tf);
         return rc;
     }
     // graph path: one captured sequence per structure (sizes of the descriptor block, grid bound,
@@ -556,7 +584,8 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
         HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipMemcpyAsync(ctx->raster_stage.dev, ctx->raster_stage.host, P.max_bytes, hipMemcpyHostToDevice,
                                       ctx->capture_stream);
-        int lrc = e == hipSuccess ? launch_frame(ctx, P, grid1, ctx->capture_stream, nullptr) : hip_fail(ctx, e, "capture memcpy");
+        int lrc = e == hipSuccess ? launch_frame(ctx, P, grid1, grid1, ctx->capture_stream, nullptr)
+                                  : hip_fail(ctx, e, "capture memcpy");
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &graph);
         if (lrc) {

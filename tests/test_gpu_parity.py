@@ -86,6 +86,7 @@ OPTION_SWEEP = [
     dict(s1_mode=3, flags=api.FLAG_NO_TINY_CULL), dict(s1_mode=2, flags=api.FLAG_ZERO_QUEUES),
     dict(s1_mode=0, s1_tris_per_thread=2), dict(s1_mode=2, s1_tris_per_thread=4, s1_block=128),
     dict(s1_mode=0, s1_tris_per_thread=4, s1_block=64, small_px=2),
+    dict(s1_mode=3, s1_tris_per_thread=1), dict(s1_mode=3, s1_tris_per_thread=4, flags=api.FLAG_ZERO_QUEUES),
 ]
 
 
