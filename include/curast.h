@@ -234,10 +234,11 @@ int curast_get_stats(curast_ctx* ctx, curast_stats* out);
 int curast_reset_stats(curast_ctx* ctx);
 
 /* Stage durations accumulated over frames run with CURAST_FLAG_TIMING, measured with HIP events
-   on the launch stream (synchronizes those events): ms[0..7] = clear, stage 1, stage-1 overflow
-   pass, stage 2, stage 3, resolve (either form), resolve backward, whole frame; *frames = number
-   of rasterized frames timed.  Batched (graph) frames contribute only the whole-frame time. */
-int curast_get_stage_times(curast_ctx* ctx, double ms[8], uint64_t* frames);
+   on the launch stream (synchronizes those events): ms[0..8] = clear, stage 1 with vertex sharing
+   (multi-draw meshes), stage 1 plain, stage-1 overflow pass, stage 2, stage 3, resolve (either
+   form), resolve backward, whole rasterized frame; *frames = number of rasterized frames timed.
+   Batched (graph) frames contribute only the whole-frame time. */
+int curast_get_stage_times(curast_ctx* ctx, double ms[9], uint64_t* frames);
 int curast_reset_stage_times(curast_ctx* ctx);
 
 /*

@@ -391,11 +391,13 @@ class Context:
         self._check(lib().curast_reset_stats(self._h))
 
     def stage_times(self) -> dict:
-        ms = (C.c_double * 8)()
+        ms = (C.c_double * 9)()
         frames = C.c_uint64()
         self._check(lib().curast_get_stage_times(self._h, ms, C.byref(frames)))
-        names = ["clear", "stage1", "stage1_overflow", "stage2", "stage3", "resolve", "resolve_backward", "frame"]
+        names = ["clear", "stage1_share", "stage1_plain", "stage1_overflow", "stage2", "stage3", "resolve",
+                 "resolve_backward", "frame"]
         d = {n: ms[i] for i, n in enumerate(names)}
+        d["stage1"] = d["stage1_share"] + d["stage1_plain"]
         d["frames"] = int(frames.value)
         return d
 

@@ -42,7 +42,9 @@ namespace {
 constexpr uint64_t kMaxIds = uint64_t(1) << 36;
 
 // Stage timing slots (CURAST_FLAG_TIMING).
-enum Slot : int { kTClear = 0, kTS1, kTS1Overflow, kTS2, kTS3, kTResolve, kTResolveBwd, kTFrame, kNumSlots };
+enum Slot : int {
+    kTClear = 0, kTS1Share, kTS1Plain, kTS1Overflow, kTS2, kTS3, kTResolve, kTResolveBwd, kTFrame, kNumSlots
+};
 
 struct TimedFrame {
     hipEvent_t ev[kNumSlots + 1];
@@ -519,23 +521,24 @@ int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, uint32_t grid_s
             e = launch_stage1_share(a1, ctx->opt.s1_tris_per_thread, stats, grid_share, s);
             if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 sharing kernel launch");
         }
+        if (tf) hipEventRecord(tf->ev[2], s);
         a1.part = 2;
         e = ctx->opt.s1_mode == 1
                 ? launch_stage1(a1, ctx->opt.s1_block, ctx->opt.s1_tris_per_thread, stats, std::max<uint32_t>(grid1, 1), s)
                 : launch_stage1_fast(a1, ctx->opt.s1_block, ctx->opt.s1_tris_per_thread, stats, std::max<uint32_t>(grid1, 1), s);
         if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 kernel launch");
     }
-    if (tf) hipEventRecord(tf->ev[2], s);
+    if (tf) hipEventRecord(tf->ev[3], s);
     e = launch_stage1_overflow(a, cus * 4, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 overflow kernel launch");
-    if (tf) hipEventRecord(tf->ev[3], s);
+    if (tf) hipEventRecord(tf->ev[4], s);
     e = launch_stage2(a, std::max<uint32_t>(1, ctx->opt.s2_waves / 4), stats, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "stage-2 kernel launch");
-    if (tf) hipEventRecord(tf->ev[4], s);
+    if (tf) hipEventRecord(tf->ev[5], s);
     e = launch_stage3(a, std::max<uint32_t>(1, ctx->opt.s3_blocks), stats, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "stage-3 kernel launch");
     if (tf) {
-        hipEventRecord(tf->ev[5], s);
+        hipEventRecord(tf->ev[6], s);
         for (int i = kTClear; i <= kTS3; ++i) tf->used[i] = 1;
     }
     return CURAST_OK;
@@ -615,20 +618,23 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
 
 void collect_timings(curast_ctx* ctx)
 {
+    // raster frames: ev[0..6] bracket clear, stage-1 sharing, stage-1 plain, overflow pass, stage 2,
+    // stage 3; resolve calls: ev[7] .. ev[8]; graph frames: ev[0] .. ev[kNumSlots]
     for (auto& f : ctx->timed) {
-        hipEventSynchronize(f.ev[kNumSlots]);
-        hipEventSynchronize(f.ev[5]);
         float ms = 0.0f;
         if (f.used[kTClear]) {
+            hipEventSynchronize(f.ev[6]);
             for (int i = kTClear; i <= kTS3; ++i)
                 if (hipEventElapsedTime(&ms, f.ev[i], f.ev[i + 1]) == hipSuccess) ctx->stage_ms[i] += ms;
-            if (hipEventElapsedTime(&ms, f.ev[0], f.ev[5]) == hipSuccess) ctx->stage_ms[kTFrame] += ms;
+            if (hipEventElapsedTime(&ms, f.ev[0], f.ev[6]) == hipSuccess) ctx->stage_ms[kTFrame] += ms;
         } else if (f.used[kTFrame]) {
+            hipEventSynchronize(f.ev[kNumSlots]);
             if (hipEventElapsedTime(&ms, f.ev[0], f.ev[kNumSlots]) == hipSuccess) ctx->stage_ms[kTFrame] += ms;
         }
         if (f.used[kTResolve] || f.used[kTResolveBwd]) {
+            hipEventSynchronize(f.ev[8]);
             const int slot = f.used[kTResolve] ? kTResolve : kTResolveBwd;
-            if (hipEventElapsedTime(&ms, f.ev[6], f.ev[7]) == hipSuccess) ctx->stage_ms[slot] += ms;
+            if (hipEventElapsedTime(&ms, f.ev[7], f.ev[8]) == hipSuccess) ctx->stage_ms[slot] += ms;
         }
         if (f.used[kTClear] || f.used[kTFrame]) ctx->timed_frames++;
         for (int i = 0; i <= kNumSlots; ++i) hipEventDestroy(f.ev[i]);
@@ -875,10 +881,10 @@ int curast_resolve(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
     HIP_TRY(ctx, hipEventRecord(ctx->resolve_stage.ev, s));
     ctx->resolve_stage.pending = true;
     TimedFrame* tf = begin_timing(ctx);
-    if (tf) hipEventRecord(tf->ev[6], s);
+    if (tf) hipEventRecord(tf->ev[7], s);
     HIP_TRY(ctx, launch_resolve(a, s));
     if (tf) {
-        hipEventRecord(tf->ev[7], s);
+        hipEventRecord(tf->ev[8], s);
         tf->used[kTResolve] = 1;
     }
     return CURAST_OK;
@@ -907,10 +913,10 @@ int curast_resolve_screen(curast_ctx* ctx, const uint64_t* visbuffer, int32_t wi
     a.out = out;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TimedFrame* tf = begin_timing(ctx);
-    if (tf) hipEventRecord(tf->ev[6], s);
+    if (tf) hipEventRecord(tf->ev[7], s);
     HIP_TRY(ctx, launch_resolve_screen(a, s));
     if (tf) {
-        hipEventRecord(tf->ev[7], s);
+        hipEventRecord(tf->ev[8], s);
         tf->used[kTResolve] = 1;
     }
     return CURAST_OK;
@@ -942,10 +948,10 @@ int curast_resolve_backward(curast_ctx* ctx, const uint64_t* visbuffer, int32_t 
     a.grad_pos = grad_pos;
     hipStream_t s = static_cast<hipStream_t>(stream);
     TimedFrame* tf = begin_timing(ctx);
-    if (tf) hipEventRecord(tf->ev[6], s);
+    if (tf) hipEventRecord(tf->ev[7], s);
     HIP_TRY(ctx, launch_resolve_backward(a, s));
     if (tf) {
-        hipEventRecord(tf->ev[7], s);
+        hipEventRecord(tf->ev[8], s);
         tf->used[kTResolveBwd] = 1;
     }
     return CURAST_OK;
