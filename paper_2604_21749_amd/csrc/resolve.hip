@@ -78,28 +78,42 @@ __global__ void __launch_bounds__(256) project_kernel(ProjectArgs a)
 // ----------------------------------------------------------------------------------------------
 // Resolve of a multi-mesh, multi-instance visibility buffer
 // ----------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) resolve_kernel(ResolveArgs a)
+constexpr uint32_t kLdsBases = 2048;   // prefix entries staged in LDS for the binary search
+
+__global__ void __launch_bounds__(256) resolve_kernel(ResolveArgs a, const uint64_t* __restrict__ bases,
+                                                      const DrawDesc* __restrict__ pairs,
+                                                      const MeshDesc* __restrict__ meshes,
+                                                      const float* const* __restrict__ attrs)
 {
+    __shared__ uint64_t s_bases[kLdsBases + 1];
+    const uint32_t np = a.n_pairs;
+    const bool staged = np <= kLdsBases;
+    if (staged) {
+        for (uint32_t i = threadIdx.x; i <= np; i += blockDim.x) s_bases[i] = bases[i];
+        __syncthreads();
+    }
+    const uint64_t* B = staged ? s_bases : bases;
     const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t npix = (uint64_t)a.W * (uint64_t)a.H;
     if (p >= npix) return;
     float* o = a.out + p * a.C;
-    const unsigned long long key = a.vis[p];
+    const unsigned long long key = gl(a.vis)[p];
     const uint64_t id = key & kIdMask;
-    if (key == kEmptyKey || id >= a.bases[a.n_pairs]) {
+    if (key == kEmptyKey || id >= B[np]) {
         write_zero(a.C, o);
         return;
     }
-    uint32_t lo = 0, hi = a.n_pairs;
+    uint32_t lo = 0, hi = np;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
-        if (a.bases[mid] <= id) lo = mid;
+        if (B[mid] <= id) lo = mid;
         else hi = mid;
     }
-    const DrawDesc& D = a.pairs[lo];
-    const MeshDesc M = a.meshes[D.mesh];
-    const uint64_t t = id - a.bases[lo];
-    const uint32_t vi[3] = {M.idx[3 * t], M.idx[3 * t + 1], M.idx[3 * t + 2]};
+    const DrawDesc& D = pairs[lo];
+    const MeshDesc& M = meshes[D.mesh];
+    const uint64_t t = id - B[lo];
+    const CURAST_GLOBAL uint32_t* ip = gl(M.idx) + 3 * t;
+    const uint32_t vi[3] = {ip[0], ip[1], ip[2]};
     if (vi[0] >= M.V || vi[1] >= M.V || vi[2] >= M.V) {
         write_zero(a.C, o);
         return;
@@ -107,7 +121,7 @@ __global__ void __launch_bounds__(256) resolve_kernel(ResolveArgs a)
     float sx[3], sy[3], w[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const float* q = M.pos + 3 * (size_t)vi[k];
+        const CURAST_GLOBAL float* q = gl(M.pos) + 3 * (size_t)vi[k];
         const Clip c = transform(D.A, q[0], q[1], q[2]);
         const float zI = 1.0f / c.w;
         sx[k] = __builtin_fmaf(c.x * zI, a.hW, a.hW);
@@ -117,7 +131,7 @@ __global__ void __launch_bounds__(256) resolve_kernel(ResolveArgs a)
     const int32_t px = (int32_t)(p % (uint64_t)a.W), py = (int32_t)(p / (uint64_t)a.W);
     Interp r;
     interp_weights(sx, sy, w, px, py, r);
-    const float* at = a.attrs[D.mesh];
+    const float* at = attrs[D.mesh];
     write_interp(r, at + (size_t)vi[0] * a.C, at + (size_t)vi[1] * a.C, at + (size_t)vi[2] * a.C, a.C, o);
 }
 
@@ -234,7 +248,7 @@ hipError_t launch_project(const float* pos, uint32_t V, const float A[12], float
 
 hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s)
 {
-    resolve_kernel<<<blocks_for((uint64_t)a.W * (uint64_t)a.H), 256, 0, s>>>(a);
+    resolve_kernel<<<blocks_for((uint64_t)a.W * (uint64_t)a.H), 256, 0, s>>>(a, a.bases, a.pairs, a.meshes, a.attrs);
     return hipGetLastError();
 }
 

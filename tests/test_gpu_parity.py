@@ -126,3 +126,37 @@ def test_north_star_entry_point_matches_mesh_list(ctx):
     vis = ctx.rasterize(g.pos, g.idx, v.vp, v.near, v.width, v.height)
     ref = O.rasterize([m], v)
     assert_vis_equal(api.as_uint64(vis), ref, "curast_rasterize")
+
+
+def test_autotune_keeps_results_and_caches(tmp_path):
+    s = W.scene_c1()
+    view = s.views[0]
+    ref = O.rasterize(s.meshes, view)
+    cache = str(tmp_path / "tune.jsonl")
+    with api.Context() as c:
+        gm = gpu_meshes(s)
+        vis = torch.empty((view.height, view.width), dtype=torch.int64, device="cuda")
+        chosen = c.autotune(gm, [view], [vis], cache_path=cache)
+        assert chosen["s1_block"] in (64, 128, 256, 512) and chosen["s1_mode"] in (0, 1, 2, 3)
+        assert_vis_equal(api.as_uint64(c.rasterize_meshes(gm, view)), ref, f"C1 with tuned {chosen}")
+    lines = open(cache).read().strip().splitlines()
+    assert len(lines) == 1 and '"key": "gfx950/' in lines[0]
+    with api.Context() as c:                     # second context: loads the entry, no re-measuring
+        again = c.autotune(gpu_meshes(s), [view], [vis], cache_path=cache)
+        assert again == chosen
+    assert len(open(cache).read().strip().splitlines()) == 1
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_stats_account_for_every_triangle(mode):
+    """Every (triangle, draw) ends in exactly one of: a cull reason, stage-1 raster, stage 2."""
+    s = W.scene_c1()
+    with api.Context(flags=api.FLAG_STATS, s1_mode=mode) as c:
+        gm = gpu_meshes(s)
+        c.rasterize_meshes(gm, s.views[0])
+        st = c.stats()
+    done = (st["culled_near"] + st["culled_frustum"] + st["culled_tiny"] + st["culled_backface"] +
+            st["s1_rasterized"] + st["q2_entries"])
+    assert st["tri_draws"] == 262146
+    assert done == st["tri_draws"], st
+    assert st["q2_entries"] >= 2 and st["q3_entries"] > 0 and st["fragments"] > 0
