@@ -74,6 +74,8 @@ typedef enum {
 #define CURAST_FLAG_STATS         0x8u  /* count per-stage events (slower; read with curast_get_stats) */
 #define CURAST_FLAG_NO_GRAPH      0x10u /* batched calls launch kernels directly instead of a hipGraph */
 #define CURAST_FLAG_TIMING        0x20u /* record HIP events around every stage (curast_get_stage_times) */
+#define CURAST_FLAG_S3_PER_PART   0x40u /* stage 3: one workgroup per tile part (Sec. 4.3) instead of
+                                           the default one workgroup per binned screen tile */
 #define CURAST_FLAG_ZERO_QUEUES   0x80000000u /* testing aid: run with stage queues of capacity 0, so
                                                  every forwarded triangle takes the overflow paths */
 

@@ -27,6 +27,7 @@ FLAG_NO_MESH_CULL = 0x4
 FLAG_STATS = 0x8
 FLAG_NO_GRAPH = 0x10
 FLAG_TIMING = 0x20
+FLAG_S3_PER_PART = 0x40
 FLAG_ZERO_QUEUES = 0x80000000
 
 EMPTY_KEY = np.uint64(0xFFFFFFFFFFFFFFFF)

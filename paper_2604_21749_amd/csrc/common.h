@@ -22,13 +22,16 @@ constexpr uint32_t kNullRecord = 0xFFFFFFFFu;
 // fits in int32 (|E| <= 2 * ext * (ext + 384) < 2^31).
 constexpr int32_t kSmallExtent = 32768 - 512;
 
-struct FrameHeader {              // 32 B
+struct FrameHeader {              // 48 B
     uint64_t total_batches;       // stage-1 work items over all segments
     uint32_t n_segs;
     uint32_t n_views;
     uint32_t batch_tris;          // triangles per work item of the plain stage-1 kernels
     uint32_t draws_per_item;      // draws per work item
     uint64_t shared_batches;      // work items [0, shared_batches) run the vertex-sharing kernel
+    uint32_t n_tiles;             // 64x64 screen tiles over all views (stage-3 bins)
+    uint32_t pad0;
+    uint64_t pad1;
 };
 
 struct ViewDesc {                 // 32 B
@@ -36,7 +39,7 @@ struct ViewDesc {                 // 32 B
     int32_t W, H;
     float hW, hH;                 // W/2, H/2 (exact)
     float near_plane;
-    uint32_t pad;
+    uint32_t tile_base;           // first stage-3 tile of this view; its tiles are row-major
 };
 
 struct MeshDesc {                 // 32 B
@@ -109,6 +112,7 @@ constexpr uint32_t kFlagNoEarlyOut = 0x2u;
 constexpr uint32_t kFlagNoMeshCull = 0x4u;
 constexpr uint32_t kFlagStats = 0x8u;
 constexpr uint32_t kFlagNoGraph = 0x10u;
+constexpr uint32_t kFlagS3PerPart = 0x40u;          // stage 3 per tile part instead of per binned tile
 constexpr uint32_t kFlagZeroQueues = 0x80000000u;   // testing aid: queue capacities of zero
 
 struct RasterArgs {
@@ -127,6 +131,9 @@ struct RasterArgs {
     uint32_t flags;
     uint32_t s1_mode;             // 0 auto, 1 exact only, 2 fast reject, 3 fast reject + vertex sharing
     uint32_t part;                // stage-1 work items: 0 all, 1 the shared prefix, 2 the rest
+    uint32_t* tile_count;         // [n_tiles] parts per tile (zeroed by the clear kernel)
+    uint32_t* tile_offset;        // [n_tiles + 1] exclusive prefix of tile_count
+    uint32_t* q3_binned;          // [q3_cap] large-record index of every part, grouped by tile
 };
 
 struct ResolveArgs {

@@ -191,6 +191,8 @@ __global__ void __launch_bounds__(256) clear_kernel(RasterArgs a)
     const uint32_t nv = a.hdr->n_views;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint32_t nt = a.hdr->n_tiles;
+    for (uint64_t i = tid; i < nt; i += stride) a.tile_count[i] = 0;
     for (uint32_t v = 0; v < nv; ++v) {
         const ViewDesc V = a.views[v];
         const uint64_t n = (uint64_t)V.W * (uint64_t)V.H;
@@ -860,12 +862,14 @@ __global__ void __launch_bounds__(256) stage2_kernel(RasterArgs a)
                         r.id = id;
                         a.large[rec] = r;
                     }
+                    const uint32_t view_ntx = (uint32_t)(V.W + kTileSize - 1) / kTileSize;
                     for (uint64_t i = lane; i < ntiles; i += 64) {
                         Q3Entry qe;
                         qe.rec = (uint32_t)rec;
                         qe.tx = (uint16_t)(tx0 + (uint32_t)(i % ntx));
                         qe.ty = (uint16_t)(ty0 + (uint32_t)(i / ntx));
                         a.q3[qbase + i] = qe;
+                        atomicAdd(a.tile_count + V.tile_base + (uint32_t)qe.ty * view_ntx + qe.tx, 1u);
                     }
                     if (lane == 0) st.add(kStQ3, (uint32_t)ntiles);
                 } else {
@@ -921,6 +925,113 @@ __global__ void __launch_bounds__(256) stage3_kernel(RasterArgs a)
         while (py < y0) py += 4;
         for (; py <= y1; py += 4)
             if (raster_pixel64(tri, px, py, r.id, V.vis, V.W, early_out)) st.add(kStFragments);
+    }
+    st.flush(a.stats);
+}
+
+// ----------------------------------------------------------------------------------------------
+// Stage 3 binned by screen tile.  The parts stage 2 produced are grouped by 64x64 tile (count,
+// scan, scatter); then one workgroup per non-empty tile walks all parts of its bin.  Lane l owns
+// the 16 pixels (l % 64, l / 64 + 4k) of the tile and keeps their running minimum keys in
+// registers, so the parts of one tile need no atomics at all and the tile costs one global 64-bit
+// atomic minimum per covered pixel however many large triangles overlap it.
+// ----------------------------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024) tile_scan_kernel(RasterArgs a)
+{
+    __shared__ uint32_t s_part[1024];
+    __shared__ uint32_t s_carry;
+    const uint32_t n = a.hdr->n_tiles;
+    if (threadIdx.x == 0) s_carry = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < n; base += 1024) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t v = i < n ? a.tile_count[i] : 0u;
+        s_part[threadIdx.x] = v;
+        __syncthreads();
+        for (uint32_t off = 1; off < 1024; off <<= 1) {           // inclusive Hillis-Steele scan
+            const uint32_t add = threadIdx.x >= off ? s_part[threadIdx.x - off] : 0u;
+            __syncthreads();
+            s_part[threadIdx.x] += add;
+            __syncthreads();
+        }
+        const uint32_t carry = s_carry;
+        if (i < n) a.tile_offset[i] = carry + s_part[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 1023) s_carry = carry + s_part[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.tile_offset[n] = s_carry;
+}
+
+__global__ void __launch_bounds__(256) tile_scatter_kernel(RasterArgs a, const ViewDesc* __restrict__ d_views)
+{
+    const unsigned long long n = min(a.counters[kCntQ3], (unsigned long long)a.q3_cap);
+    for (unsigned long long e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (uint64_t)gridDim.x * blockDim.x) {
+        const Q3Entry q = a.q3[e];
+        if (q.rec == kNullRecord) continue;
+        const ViewDesc& V = d_views[a.large[q.rec].view];
+        const uint32_t t = V.tile_base + (uint32_t)q.ty * ((uint32_t)(V.W + kTileSize - 1) / kTileSize) + q.tx;
+        const uint32_t left = atomicSub(a.tile_count + t, 1u);    // left..1: a distinct slot per part
+        a.q3_binned[a.tile_offset[t] + left - 1] = q.rec;
+    }
+}
+
+template <bool STATS>
+__global__ void __launch_bounds__(256) stage3_tile_kernel(RasterArgs a, const ViewDesc* __restrict__ d_views)
+{
+    const uint32_t n_tiles = a.hdr->n_tiles;
+    const uint32_t nv = a.hdr->n_views;
+    const bool early_out = !(a.flags & kFlagNoEarlyOut);
+    const int32_t col = threadIdx.x & 63;
+    const int32_t row0 = threadIdx.x >> 6;
+    StatAcc<STATS> st;
+    for (uint32_t t = blockIdx.x; t < n_tiles; t += gridDim.x) {
+        const uint32_t begin = a.tile_offset[t], end = a.tile_offset[t + 1];
+        if (begin == end) continue;
+        // the view that owns tile t (views are few: linear scan of their tile bases)
+        uint32_t v = 0;
+        while (v + 1 < nv && d_views[v + 1].tile_base <= t) ++v;
+        const ViewDesc V = d_views[v];
+        const uint32_t ntx = (uint32_t)(V.W + kTileSize - 1) / kTileSize;
+        const uint32_t local = t - V.tile_base;
+        const int32_t px = (int32_t)(local % ntx) * kTileSize + col;
+        const int32_t py0 = (int32_t)(local / ntx) * kTileSize + row0;
+        unsigned long long best[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) best[k] = kEmptyKey;
+        for (uint32_t j = begin; j < end; ++j) {
+            const LargeTri r = a.large[a.q3_binned[j]];
+            Tri64 tri;
+            if (!setup_tri64(r.X, r.Y, r.zI, V.W, V.H, tri)) continue;
+            if (px < tri.px0 || px > tri.px1) continue;
+            // edge values at (px, py0), stepped by four rows
+            int64_t e[3];
+            const int64_t step[3] = {(int64_t)tri.dx[0] * 1024, (int64_t)tri.dx[1] * 1024, (int64_t)tri.dx[2] * 1024};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) e[k] = edge64(tri, k, px, py0);
+            const float area_f = (float)tri.area;
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                const int32_t py = py0 + 4 * k;
+                if (py >= tri.py0 && py <= tri.py1 &&
+                    ((e[0] + tri.bias[0]) | (e[1] + tri.bias[1]) | (e[2] + tri.bias[2])) >= 0) {
+                    const float depth = frag_depth((float)e[0], (float)e[1], (float)e[2], tri.zI, area_f);
+                    const unsigned long long key = make_key(depth, r.id);
+                    best[k] = key < best[k] ? key : best[k];
+                    st.add(kStFragments);
+                }
+                e[0] += step[0];
+                e[1] += step[1];
+                e[2] += step[2];
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int32_t py = py0 + 4 * k;
+            if (best[k] != kEmptyKey && px < V.W && py < V.H)
+                write_fragment(V.vis + (size_t)py * (size_t)V.W + (size_t)px, best[k], early_out);
+        }
     }
     st.flush(a.stats);
 }
@@ -1022,6 +1133,15 @@ hipError_t launch_stage2(const RasterArgs& a, uint32_t grid, bool stats, hipStre
 {
     if (stats) stage2_kernel<true><<<grid, 256, 0, s>>>(a);
     else stage2_kernel<false><<<grid, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage3_binned(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s)
+{
+    tile_scan_kernel<<<1, 1024, 0, s>>>(a);
+    tile_scatter_kernel<<<grid, 256, 0, s>>>(a, a.views);
+    if (stats) stage3_tile_kernel<true><<<grid, 256, 0, s>>>(a, a.views);
+    else stage3_tile_kernel<false><<<grid, 256, 0, s>>>(a, a.views);
     return hipGetLastError();
 }
 

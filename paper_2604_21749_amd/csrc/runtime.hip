@@ -29,6 +29,7 @@ hipError_t launch_stage1_share(const RasterArgs& a, uint32_t tpt, bool stats, ui
 hipError_t launch_stage1_overflow(const RasterArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_stage2(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
 hipError_t launch_stage3(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
+hipError_t launch_stage3_binned(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
 hipError_t launch_project(const float* pos, uint32_t V, const float A[12], float hW, float hH, float* out, hipStream_t s);
 hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s);
 hipError_t launch_resolve_screen(const ScreenArgs& a, hipStream_t s);
@@ -83,6 +84,10 @@ struct curast_ctx {
     uint32_t q2_alloc = 0, large_alloc = 0, q3_alloc = 0;
     unsigned long long* counters = nullptr;
     unsigned long long* stats = nullptr;
+    uint32_t* tile_count = nullptr;
+    uint32_t* tile_offset = nullptr;
+    uint32_t* q3_binned = nullptr;
+    uint32_t tiles_alloc = 0;
     hipStream_t capture_stream = nullptr;
     std::vector<GraphEntry> graphs;
     std::vector<TimedFrame> timed;
@@ -152,6 +157,22 @@ void drop_graphs(curast_ctx* ctx)
     ctx->graphs.clear();
 }
 
+int ensure_tiles(curast_ctx* ctx, uint32_t n_tiles)
+{
+    if (n_tiles + 1 <= ctx->tiles_alloc) return CURAST_OK;
+    const uint32_t n = std::max<uint32_t>(n_tiles + 1, 4096);
+    if (ctx->tile_count) hipFree(ctx->tile_count);
+    if (ctx->tile_offset) hipFree(ctx->tile_offset);
+    ctx->tile_count = ctx->tile_offset = nullptr;
+    ctx->tiles_alloc = 0;
+    if (hipMalloc(&ctx->tile_count, sizeof(uint32_t) * n) != hipSuccess ||
+        hipMalloc(&ctx->tile_offset, sizeof(uint32_t) * n) != hipSuccess)
+        return fail(ctx, CURAST_E_OOM, "tile bin allocation failed");
+    ctx->tiles_alloc = n;
+    drop_graphs(ctx);
+    return CURAST_OK;
+}
+
 int ensure_staging(curast_ctx* ctx, Staging& st, size_t bytes)
 {
     if (st.pending) {
@@ -190,7 +211,11 @@ int ensure_queues(curast_ctx* ctx)
         if (ctx->q3) hipFree(ctx->q3);
         ctx->q3 = nullptr;
         ctx->q3_alloc = 0;
+        if (ctx->q3_binned) hipFree(ctx->q3_binned);
+        ctx->q3_binned = nullptr;
         if (hipMalloc(&ctx->q3, sizeof(Q3Entry) * (size_t)q3) != hipSuccess) return fail(ctx, CURAST_E_OOM, "Q3 allocation failed");
+        if (hipMalloc(&ctx->q3_binned, sizeof(uint32_t) * (size_t)q3) != hipSuccess)
+            return fail(ctx, CURAST_E_OOM, "Q3 bin allocation failed");
         ctx->q3_alloc = q3;
         drop_graphs(ctx);
     }
@@ -369,7 +394,8 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
         d.hW = 0.5f * (float)views[v].width;
         d.hH = 0.5f * (float)views[v].height;
         d.near_plane = views[v].near_plane;
-        d.pad = 0;
+        d.tile_base = P.hdr.n_tiles;
+        P.hdr.n_tiles += (uint32_t)(((d.W + kTileSize - 1) / kTileSize) * ((d.H + kTileSize - 1) / kTileSize));
         P.total_pixels += (uint64_t)d.W * (uint64_t)d.H;
     }
     P.meshes.resize(M);
@@ -487,6 +513,9 @@ RasterArgs make_args(curast_ctx* ctx, const Plan& P)
     a.flags = ctx->opt.flags;
     a.s1_mode = ctx->opt.s1_mode;
     a.part = 0;
+    a.tile_count = ctx->tile_count;
+    a.tile_offset = ctx->tile_offset;
+    a.q3_binned = ctx->q3_binned;
     return a;
 }
 
@@ -535,7 +564,8 @@ int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, uint32_t grid_s
     e = launch_stage2(a, std::max<uint32_t>(1, ctx->opt.s2_waves / 4), stats, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "stage-2 kernel launch");
     if (tf) hipEventRecord(tf->ev[5], s);
-    e = launch_stage3(a, std::max<uint32_t>(1, ctx->opt.s3_blocks), stats, s);
+    e = (ctx->opt.flags & kFlagS3PerPart) ? launch_stage3(a, std::max<uint32_t>(1, ctx->opt.s3_blocks), stats, s)
+                                          : launch_stage3_binned(a, std::max<uint32_t>(1, ctx->opt.s3_blocks), stats, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "stage-3 kernel launch");
     if (tf) {
         hipEventRecord(tf->ev[6], s);
@@ -555,6 +585,8 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
     int rc = build_plan(ctx, ctx->opt, meshes, M, views, n_views, P);
     if (rc) return rc;
     rc = ensure_queues(ctx);
+    if (rc) return rc;
+    rc = ensure_tiles(ctx, P.hdr.n_tiles);
     if (rc) return rc;
     const size_t bytes = use_graph ? P.max_bytes : P.bytes;
     rc = ensure_staging(ctx, ctx->raster_stage, bytes);
@@ -773,6 +805,9 @@ int curast_destroy(curast_ctx* ctx)
     }
     if (ctx->q2) hipFree(ctx->q2);
     if (ctx->q3) hipFree(ctx->q3);
+    if (ctx->q3_binned) hipFree(ctx->q3_binned);
+    if (ctx->tile_count) hipFree(ctx->tile_count);
+    if (ctx->tile_offset) hipFree(ctx->tile_offset);
     if (ctx->large) hipFree(ctx->large);
     if (ctx->counters) hipFree(ctx->counters);
     if (ctx->stats) hipFree(ctx->stats);

@@ -87,6 +87,8 @@ OPTION_SWEEP = [
     dict(s1_mode=0, s1_tris_per_thread=2), dict(s1_mode=2, s1_tris_per_thread=4, s1_block=128),
     dict(s1_mode=0, s1_tris_per_thread=4, s1_block=64, small_px=2),
     dict(s1_mode=3, s1_tris_per_thread=1), dict(s1_mode=3, s1_tris_per_thread=4, flags=api.FLAG_ZERO_QUEUES),
+    dict(flags=api.FLAG_S3_PER_PART), dict(flags=api.FLAG_S3_PER_PART, medium_px=1),
+    dict(medium_px=1, s3_blocks=3), dict(medium_px=64, q3_capacity=7),
 ]
 
 
