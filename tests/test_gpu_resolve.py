@@ -1,0 +1,89 @@
+"""GPU parity of the resolve family (needs an MI355X): project, resolve, screen resolve, backward."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from helpers import assert_resolve_close, assert_vis_equal
+from paper_2604_21749_amd import api
+from paper_2604_21749_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = api.Context()
+    yield c
+    c.close()
+
+
+def test_project_is_bit_exact(ctx):
+    s = W.scene_c1()
+    for m in s.meshes:
+        g = api.GpuMesh.from_host(m)
+        got = ctx.project(g, s.views[0]).cpu().numpy()
+        assert np.array_equal(got, O.project(m, s.views[0]))
+    t = W.random_tiny_scene(3, n_instances=5)
+    g = api.GpuMesh.from_host(t.meshes[0])
+    for i in range(5):
+        assert np.array_equal(ctx.project(g, t.views[0], instance=i).cpu().numpy(),
+                              O.project(t.meshes[0], t.views[0], instance=i))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_resolve_instanced_multimesh(ctx, seed):
+    scenes = [W.random_tiny_scene(seed, n_instances=4, n_tris=30, spread=3.0),
+              W.random_tiny_scene(seed + 100, n_tris=20, near_crossing=True)]
+    meshes = [scenes[0].meshes[0], scenes[1].meshes[0]]
+    view = scenes[0].views[0]
+    gm = [api.GpuMesh.from_host(m) for m in meshes]
+    vis = ctx.rasterize_meshes(gm, view)
+    ref = O.rasterize(meshes, view)
+    assert_vis_equal(api.as_uint64(vis), ref, f"multi-mesh seed {seed}")
+    out = ctx.resolve(gm, view, vis, [g.attrs for g in gm]).cpu().numpy()
+    assert_resolve_close(out, O.resolve(meshes, view, ref, [m.attrs for m in meshes]), "multi-mesh resolve")
+
+
+def test_screen_resolve_equals_resolve_and_ignores_other_meshes(ctx):
+    s = W.scene_c1()
+    view = s.views[0]
+    gm = [api.GpuMesh.from_host(m) for m in s.meshes]
+    vis = ctx.rasterize_meshes(gm, view)
+    full = ctx.resolve(gm, view, vis, [g.attrs for g in gm]).cpu().numpy()
+    ids = O.key_id(api.as_uint64(vis))
+    covered = api.as_uint64(vis) != O.EMPTY
+    # the ground quad alone, as mesh 1 with id_base = T_sphere
+    g = gm[1]
+    pss = ctx.project(g, view)
+    out = ctx.resolve_screen(vis, g.idx, pss, g.attrs, id_base=262144).cpu().numpy()
+    ground = covered & (ids >= 262144)
+    assert ground.sum() > 50000
+    assert np.array_equal(out[ground], full[ground])
+    assert np.all(out[~ground] == 0)
+    ref = O.resolve_screen(api.as_uint64(vis), s.meshes[1].idx, 262144, pss.cpu().numpy(), s.meshes[1].attrs)
+    assert np.array_equal(out, ref)
+
+
+def test_backward_small_scene_vs_fp64(ctx):
+    s = W.scene_c5(n=256)
+    m = s.meshes[0]
+    view = W.View(s.views[0].vp, s.views[0].near, 200, 160)
+    g = api.GpuMesh.from_host(m)
+    vis = ctx.rasterize_meshes([g], view)
+    pss = ctx.project(g, view)
+    rng = np.random.default_rng(4)
+    gout = rng.normal(size=(view.height, view.width, 3)).astype(np.float32)
+    ga = torch.zeros_like(g.attrs)
+    gp = torch.zeros_like(pss)
+    ctx.resolve_backward(vis, g.idx, pss, g.attrs, torch.from_numpy(gout).cuda(), ga, gp)
+    ra, rp = O.resolve_screen_backward_f64(api.as_uint64(vis), m.idx, 0, pss.cpu().numpy(), m.attrs,
+                                           gout.astype(np.float64))
+    for got, ref, what in ((ga.cpu().numpy(), ra, "attrs"), (gp.cpu().numpy(), rp, "positions")):
+        scale = np.maximum(np.abs(ref), 1e-3 * np.sqrt(np.mean(ref ** 2)))
+        err = np.abs(got.astype(np.float64) - ref) / scale
+        assert err.max() <= 1e-3, f"{what}: {err.max()}"
+    # pixels of other meshes (id_base shifted past every ID) contribute nothing
+    ga2 = torch.zeros_like(g.attrs)
+    ctx.resolve_backward(vis, g.idx, pss, g.attrs, torch.from_numpy(gout).cuda(), ga2, None, id_base=1 << 30)
+    assert float(ga2.abs().sum()) == 0.0
