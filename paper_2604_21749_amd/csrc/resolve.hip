@@ -173,57 +173,57 @@ __global__ void __launch_bounds__(256) resolve_screen_kernel(ScreenArgs a)
     write_interp(r, a.attrs + (size_t)vi[0] * a.C, a.attrs + (size_t)vi[1] * a.C, a.attrs + (size_t)vi[2] * a.C, a.C, o);
 }
 
-// dL/da_k = g b_k;  G_k = g . a_k;  dL/dq_j = (G_j - sum_k G_k b_k) / s;
-// dL/dlambda_j = dL/dq_j zI_j;  dL/dw_j = -(dL/dq_j lambda_j) zI_j^2;
-// lambda_0 = d1 x d2, lambda_1 = d2 x d0, lambda_2 = d0 x d1 with d_k = s_k - pixel centre.
+// Backward with visibility held fixed.  The chain rule of one pixel has cancelling terms
+// (G_j - sum_k G_k b_k, the cross-product partials of sliver triangles), so it is evaluated in
+// fp64 from the fp32 inputs and each contribution is rounded once into the fp32 atomic sums:
+//   dL/da_k = g b_k;  G_k = g . a_k;  dL/dq_j = (G_j - sum_k G_k b_k) / s;
+//   dL/dlambda_j = dL/dq_j zI_j;  dL/dw_j = -(dL/dq_j lambda_j) zI_j^2;
+//   lambda_0 = d1 x d2, lambda_1 = d2 x d0, lambda_2 = d0 x d1 with d_k = s_k - pixel centre.
 __global__ void __launch_bounds__(256) resolve_backward_kernel(ScreenArgs a)
 {
     const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= (uint64_t)a.W * (uint64_t)a.H) return;
     uint32_t vi[3];
     if (!screen_tri(a, p, vi)) return;
-    float sx[3], sy[3], w[3];
+    const double cx = (double)(p % (uint64_t)a.W) + 0.5, cy = (double)(p / (uint64_t)a.W) + 0.5;
+    double d[3][2], zI[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        sx[k] = a.pos_ss[3 * (size_t)vi[k]];
-        sy[k] = a.pos_ss[3 * (size_t)vi[k] + 1];
-        w[k] = a.pos_ss[3 * (size_t)vi[k] + 2];
+        d[k][0] = (double)a.pos_ss[3 * (size_t)vi[k]] - cx;
+        d[k][1] = (double)a.pos_ss[3 * (size_t)vi[k] + 1] - cy;
+        zI[k] = 1.0 / (double)a.pos_ss[3 * (size_t)vi[k] + 2];
     }
-    Interp r;
-    interp_weights(sx, sy, w, (int32_t)(p % (uint64_t)a.W), (int32_t)(p / (uint64_t)a.W), r);
+    const double lam[3] = {d[1][0] * d[2][1] - d[1][1] * d[2][0], d[2][0] * d[0][1] - d[2][1] * d[0][0],
+                           d[0][0] * d[1][1] - d[0][1] * d[1][0]};
+    const double q[3] = {lam[0] * zI[0], lam[1] * zI[1], lam[2] * zI[2]};
+    const double sum = q[0] + q[1] + q[2];
+    const double b[3] = {q[0] / sum, q[1] / sum, q[2] / sum};
     const float* g = a.grad_out + p * a.C;
-    float G[3] = {0.0f, 0.0f, 0.0f};
+    double G[3] = {0.0, 0.0, 0.0};
     for (uint32_t c = 0; c < a.C; ++c) {
-        const float gc = g[c];
+        const double gc = g[c];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const float ac = a.attrs[(size_t)vi[k] * a.C + c];
-            G[k] = G[k] + gc * ac;
-            unsafeAtomicAdd(a.grad_attr + (size_t)vi[k] * a.C + c, gc * r.b[k]);
+            G[k] += gc * (double)a.attrs[(size_t)vi[k] * a.C + c];
+            unsafeAtomicAdd(a.grad_attr + (size_t)vi[k] * a.C + c, (float)(gc * b[k]));
         }
     }
     if (!a.grad_pos) return;
-    const float Gb = (G[0] * r.b[0] + G[1] * r.b[1]) + G[2] * r.b[2];
-    float L[3], dw[3];
+    const double Gb = G[0] * b[0] + G[1] * b[1] + G[2] * b[2];
+    double L[3], dw[3];
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        const float Q = (G[j] - Gb) / r.s;
-        L[j] = Q * r.zI[j];
-        dw[j] = -((Q * r.lam[j]) * r.zI[j]) * r.zI[j];
+        const double Q = (G[j] - Gb) / sum;
+        L[j] = Q * zI[j];
+        dw[j] = -(Q * lam[j]) * zI[j] * zI[j];
     }
-    const float(*d)[2] = r.d;
-    float gx[3], gy[3];
-    gx[0] = L[2] * d[1][1] - L[1] * d[2][1];
-    gy[0] = L[1] * d[2][0] - L[2] * d[1][0];
-    gx[1] = L[0] * d[2][1] - L[2] * d[0][1];
-    gy[1] = L[2] * d[0][0] - L[0] * d[2][0];
-    gx[2] = L[1] * d[0][1] - L[0] * d[1][1];
-    gy[2] = L[0] * d[1][0] - L[1] * d[0][0];
+    const double gx[3] = {L[2] * d[1][1] - L[1] * d[2][1], L[0] * d[2][1] - L[2] * d[0][1], L[1] * d[0][1] - L[0] * d[1][1]};
+    const double gy[3] = {L[1] * d[2][0] - L[2] * d[1][0], L[2] * d[0][0] - L[0] * d[2][0], L[0] * d[1][0] - L[1] * d[0][0]};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        unsafeAtomicAdd(a.grad_pos + 3 * (size_t)vi[k] + 0, gx[k]);
-        unsafeAtomicAdd(a.grad_pos + 3 * (size_t)vi[k] + 1, gy[k]);
-        unsafeAtomicAdd(a.grad_pos + 3 * (size_t)vi[k] + 2, dw[k]);
+        unsafeAtomicAdd(a.grad_pos + 3 * (size_t)vi[k] + 0, (float)gx[k]);
+        unsafeAtomicAdd(a.grad_pos + 3 * (size_t)vi[k] + 1, (float)gy[k]);
+        unsafeAtomicAdd(a.grad_pos + 3 * (size_t)vi[k] + 2, (float)dw[k]);
     }
 }
 
