@@ -76,6 +76,11 @@ typedef enum {
 #define CURAST_FLAG_TIMING        0x20u /* record HIP events around every stage (curast_get_stage_times) */
 #define CURAST_FLAG_S3_PER_PART   0x40u /* stage 3: one workgroup per tile part (Sec. 4.3) instead of
                                            the default one workgroup per binned screen tile */
+#define CURAST_FLAG_NO_FAST_INTERIOR 0x80u /* stage 1: no prescaled window rows for draws whose
+                                                bounding sphere lies well inside the view frustum */
+#define CURAST_FLAG_NO_PAIRS      0x100u /* stage 1, meshes with several draws: no edge-sharing
+                                            triangle pairs (each triangle takes three window
+                                            positions per draw) */
 #define CURAST_FLAG_ZERO_QUEUES   0x80000000u /* testing aid: run with stage queues of capacity 0, so
                                                  every forwarded triangle takes the overflow paths */
 
@@ -84,7 +89,8 @@ typedef struct {
     uint32_t small_px;          /* stage-1 limit on pixel centres in the clamped bbox (default 128, Sec. 4) */
     uint32_t medium_px;         /* stage-2 limit (default 4096, Sec. 4) */
     uint32_t s1_block;          /* stage-1 workgroup size: 64, 128, 256 or 512 (default 256, Sec. 4.1) */
-    uint32_t s1_tris_per_thread;/* triangles per thread per stage-1 work item: 1, 2 or 4 (default 1) */
+    uint32_t s1_tris_per_thread;/* triangles per thread per stage-1 work item of a mesh drawn once:
+                                   1, 2 or 4 (default 4) */
     uint32_t s1_draws_per_item; /* (instance x view) draws per stage-1 work item (default 64, Sec. 4.5) */
     uint32_t s2_waves;          /* persistent stage-2 wavefronts (default 4 per CU) */
     uint32_t s3_blocks;         /* persistent stage-3 workgroups (default 2 per CU) */
@@ -96,7 +102,11 @@ typedef struct {
     uint32_t s1_mode;           /* stage-1 kernel: 0 = auto (currently 2), 1 = one lane per
                                    triangle with exact arithmetic only, 2 = conservative fast reject
                                    with approximate reciprocals and wave-compacted exact work,
-                                   3 = same as 2 (reserved) */
+                                   3 = every mesh through the wave-level vertex-sharing kernel
+                                   (each vertex transformed once per wave and draw) */
+    uint32_t s1_multi_tris_per_thread; /* as s1_tris_per_thread, for meshes with two or more
+                                   surviving draws, which stage 1 takes in a launch of its own
+                                   (default 2) */
 } curast_options;
 
 typedef struct {
@@ -236,9 +246,10 @@ int curast_get_stats(curast_ctx* ctx, curast_stats* out);
 int curast_reset_stats(curast_ctx* ctx);
 
 /* Stage durations accumulated over frames run with CURAST_FLAG_TIMING, measured with HIP events
-   on the launch stream (synchronizes those events): ms[0..8] = clear, stage 1 with vertex sharing
-   (multi-draw meshes), stage 1 plain, stage-1 overflow pass, stage 2, stage 3, resolve (either
-   form), resolve backward, whole rasterized frame; *frames = number of rasterized frames timed.
+   on the launch stream (synchronizes those events): ms[0..8] = clear, stage-1 launch over the
+   meshes with two or more draws (all meshes when s1_mode = 3), stage-1 launch over the other
+   meshes, stage-1 overflow pass, stage 2, stage 3, resolve (either form), resolve backward, whole
+   rasterized frame; *frames = number of rasterized frames timed.
    Batched (graph) frames contribute only the whole-frame time. */
 int curast_get_stage_times(curast_ctx* ctx, double ms[9], uint64_t* frames);
 int curast_reset_stage_times(curast_ctx* ctx);

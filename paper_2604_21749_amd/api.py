@@ -28,6 +28,8 @@ FLAG_STATS = 0x8
 FLAG_NO_GRAPH = 0x10
 FLAG_TIMING = 0x20
 FLAG_S3_PER_PART = 0x40
+FLAG_NO_FAST_INTERIOR = 0x80
+FLAG_NO_PAIRS = 0x100
 FLAG_ZERO_QUEUES = 0x80000000
 
 EMPTY_KEY = np.uint64(0xFFFFFFFFFFFFFFFF)
@@ -42,7 +44,8 @@ class CurastError(RuntimeError):
 class Options(C.Structure):
     _fields_ = [(n, C.c_uint32) for n in (
         "small_px", "medium_px", "s1_block", "s1_tris_per_thread", "s1_draws_per_item", "s2_waves",
-        "s3_blocks", "q2_capacity", "q3_capacity", "large_capacity", "flags", "s1_mode")]
+        "s3_blocks", "q2_capacity", "q3_capacity", "large_capacity", "flags", "s1_mode",
+        "s1_multi_tris_per_thread")]
 
 
 class MeshStruct(C.Structure):
@@ -395,10 +398,10 @@ class Context:
         ms = (C.c_double * 9)()
         frames = C.c_uint64()
         self._check(lib().curast_get_stage_times(self._h, ms, C.byref(frames)))
-        names = ["clear", "stage1_share", "stage1_plain", "stage1_overflow", "stage2", "stage3", "resolve",
+        names = ["clear", "stage1_multi", "stage1_single", "stage1_overflow", "stage2", "stage3", "resolve",
                  "resolve_backward", "frame"]
         d = {n: ms[i] for i, n in enumerate(names)}
-        d["stage1"] = d["stage1_share"] + d["stage1_plain"]
+        d["stage1"] = d["stage1_multi"] + d["stage1_single"]
         d["frames"] = int(frames.value)
         return d
 

@@ -61,6 +61,7 @@ const Field kFields[] = {
     {"q3_capacity", &curast_options::q3_capacity},
     {"large_capacity", &curast_options::large_capacity},
     {"s1_mode", &curast_options::s1_mode},
+    {"s1_multi_tris_per_thread", &curast_options::s1_multi_tris_per_thread},
 };
 
 std::string to_json(const std::string& key, const curast_options& o)
@@ -180,7 +181,10 @@ extern "C" int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint3
         {&curast_options::s2_waves, {cus * 2, cus * 4, cus * 8}},
         {&curast_options::s3_blocks, {cus, cus * 2, cus * 4}},
     };
-    if (max_draws > 1) axes.push_back({&curast_options::s1_draws_per_item, {8, 16, 32, 64, 128, 256}});
+    if (max_draws > 1) {
+        axes.push_back({&curast_options::s1_multi_tris_per_thread, {1, 2, 4}});
+        axes.push_back({&curast_options::s1_draws_per_item, {8, 16, 32, 64, 128, 256}});
+    }
     for (int pass = 0; pass < 2; ++pass) {
         bool improved = false;
         for (const Axis& ax : axes) {

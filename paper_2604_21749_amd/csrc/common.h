@@ -28,18 +28,20 @@ struct FrameHeader {              // 48 B
     uint32_t n_views;
     uint32_t batch_tris;          // triangles per work item of the plain stage-1 kernels
     uint32_t draws_per_item;      // draws per work item
-    uint64_t shared_batches;      // work items [0, shared_batches) run the vertex-sharing kernel
+    uint64_t shared_batches;      // work items [0, shared_batches) belong to meshes drawn more than once
     uint32_t n_tiles;             // 64x64 screen tiles over all views (stage-3 bins)
     uint32_t pad0;
     uint64_t pad1;
 };
 
-struct ViewDesc {                 // 32 B
+struct ViewDesc {                 // 48 B
     unsigned long long* vis;      // [H][W]
     int32_t W, H;
     float hW, hH;                 // W/2, H/2 (exact)
     float near_plane;
     uint32_t tile_base;           // first stage-3 tile of this view; its tiles are row-major
+    float wmax, hmax;             // W - 1, H - 1 (exact)
+    uint32_t pad[2];
 };
 
 struct MeshDesc {                 // 32 B
@@ -67,10 +69,11 @@ struct Segment {                  // 32 B
 // Bit 31 of `view` (kDrawInterior) marks draws whose bounding sphere the host proved to lie in
 // front of the near plane and inside |x|, |y| <= 1.99 w: no vertex of such a draw needs the
 // per-vertex near/guard tests of the fast stage-1 path.
-struct DrawDesc {                 // 64 B
-    float A[12];
+struct DrawDesc {                 // 96 B
+    float A[12];                  // rows x, y, w of VP * X (the exact transform)
+    float R[8];                   // interior draws: hW (row x + row w), hH (row y + row w)
     uint64_t id_base;
-    uint32_t view;
+    uint32_t view;                // view index | kDrawInterior
     uint32_t mesh;
 };
 constexpr uint32_t kDrawInterior = 0x80000000u;
@@ -113,6 +116,8 @@ constexpr uint32_t kFlagNoMeshCull = 0x4u;
 constexpr uint32_t kFlagStats = 0x8u;
 constexpr uint32_t kFlagNoGraph = 0x10u;
 constexpr uint32_t kFlagS3PerPart = 0x40u;          // stage 3 per tile part instead of per binned tile
+constexpr uint32_t kFlagNoFastInterior = 0x80u;     // no prescaled interior draws in stage 1
+constexpr uint32_t kFlagNoPairs = 0x100u;           // no edge-sharing pairs in stage 1
 constexpr uint32_t kFlagZeroQueues = 0x80000000u;   // testing aid: queue capacities of zero
 
 struct RasterArgs {
@@ -129,7 +134,7 @@ struct RasterArgs {
     uint32_t q2_cap, large_cap, q3_cap;
     uint32_t small_px, medium_px;
     uint32_t flags;
-    uint32_t s1_mode;             // 0 auto, 1 exact only, 2 fast reject, 3 fast reject + vertex sharing
+    uint32_t s1_mode;             // 0 auto (= 2), 1 exact only, 2 fast reject, 3 vertex sharing for every mesh
     uint32_t part;                // stage-1 work items: 0 all, 1 the shared prefix, 2 the rest
     uint32_t* tile_count;         // [n_tiles] parts per tile (zeroed by the clear kernel)
     uint32_t* tile_offset;        // [n_tiles + 1] exclusive prefix of tile_count

@@ -4,6 +4,8 @@
 // mapping, ballot-compacted queues and in-place overflow handling are this implementation's.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "device.h"
 
 namespace curast {
@@ -346,23 +348,32 @@ __global__ void __launch_bounds__(BLOCK) stage1_kernel(RasterArgs a, CURAST_DESC
 }
 
 // ----------------------------------------------------------------------------------------------
-// Stage 1, fast variant.  Two changes to the lane-per-triangle loop, neither of which changes a
-// single fragment:
+// Stage 1, fast variant.  Changes to the lane-per-triangle loop, none of which changes a single
+// fragment:
 //  (1) a conservative reject with approximate window positions (v_rcp_f32 instead of the correctly
 //      rounded 1/w) and a bounding box widened by kFastMargin pixels: when the widened box holds no
 //      pixel centre inside the view, the exact box cannot hold one either, so the triangle is
 //      culled without the exact arithmetic (almost every triangle of a dense mesh ends here);
-//  (2) the few undecided triangles are appended to a list in LDS and run through the exact
-//      classification and rasterization together, so no lane idles while one lane of its
-//      wavefront takes the long path.
-// With SHARE, work items that draw the same triangles for several instances/views first
-// deduplicate the batch's vertex indices in an LDS hash table; each unique vertex is then
-// transformed once per draw instead of once per referencing triangle (vertex reuse through LDS).
+//  (2) the few undecided (triangle, draw) pairs are appended to a list in LDS and run through the
+//      exact classification and rasterization together, so no lane idles while one lane of its
+//      wavefront takes the long path;
+//  (3) interior draws (bounding sphere inside |x|, |y| <= 1.99 w, w >= 1.001 near, checked on the
+//      host) skip the per-vertex range tests and take their window position from two prescaled
+//      rows, x'' = hW (row x + row w) . (v, 1) and likewise y'', so that x''/w is the window x;
+//  (4) with PAIRS a lane owns consecutive triangles; when every lane's second triangle shares an
+//      edge with its first (one vertex of each outside the other), the pair needs four window
+//      positions instead of six.
 //
-// Error bound of the fast positions (|x|, |y| <= 2w, near <= w < 1e30, W, H <= 16384): rcp has
-// at most 1 ulp error, so |x*r - x/w| <= 2^-20 and the approximate window coordinate differs from
-// the exact snapped one by at most 1.625 hW 2^-20 + 2^-9 <= 0.0147 px, plus 2^-9 px of rounding
-// in the box arithmetic: below the margin of 1/32 px.
+// Error bounds (u = 2^-24; S_r = sum_j |row_rj| |v_j| + |row_r3| over the vertex, w its depth):
+//  exact path: x and w carry at most 3u S_x and 3u S_w of fma-chain error, and 1/w, x*zI and the
+//      window fma add 7u hW; snapping adds 2^-9 px;
+//  fast path from the exact x, w (general draws, |x|, |y| <= 2w): rcp (1 ulp) and the two roundings
+//      after it differ from the exact path by at most 1.625 hW 2^-20 px;
+//  prescaled path: rounding the rows to binary32 and the fma chain give |x'' - hW (x + w)| <=
+//      4u hW (S_x + S_w), the reciprocal of the same w adds 9u S_w hW / w, and rcp with the
+//      multiply 9u hW, so the fast position is within hW u ((7 S_x + 19 S_w) / w + 16) of the
+//      exact one; the host enables the path for a draw only when this bound over its bounding
+//      sphere, plus 2^-9 px of snapping and 3.1u hW of box arithmetic, is below kFastMargin.
 // ----------------------------------------------------------------------------------------------
 constexpr float kFastMargin = 1.0f / 32.0f;
 constexpr float kFastGuard = 2.0f;
@@ -383,26 +394,44 @@ __device__ __forceinline__ float2 fast_window_interior(const Clip& c, const View
     return make_float2(__builtin_fmaf(c.x * r, V.hW, V.hW), __builtin_fmaf(c.y * r, V.hH, V.hH));
 }
 
-// True when the triangle provably covers no pixel centre of the view.
-__device__ __forceinline__ bool fast_reject(float2 a, float2 b, float2 c, const ViewDesc& V, bool tiny_cull)
+// Window position of a vertex of an interior draw from the draw's prescaled rows (see above).
+__device__ __forceinline__ float2 fast_window_prescaled(const float* R, const float* Aw, float vx, float vy, float vz)
 {
-    if (__builtin_isnan(a.x) || __builtin_isnan(b.x) || __builtin_isnan(c.x)) return false;
-    // centre of pixel p is p + 0.5: p in [ceil(min - m - 0.5), floor(max + m - 0.5)]
-    const float xlo = __builtin_ceilf(fminf(a.x, fminf(b.x, c.x)) - (kFastMargin + 0.5f));
-    const float xhi = __builtin_floorf(fmaxf(a.x, fmaxf(b.x, c.x)) + (kFastMargin - 0.5f));
-    const float ylo = __builtin_ceilf(fminf(a.y, fminf(b.y, c.y)) - (kFastMargin + 0.5f));
-    const float yhi = __builtin_floorf(fmaxf(a.y, fmaxf(b.y, c.y)) + (kFastMargin - 0.5f));
-    const float wmax = (float)(V.W - 1), hmax = (float)(V.H - 1);
-    if (xhi < 0.0f || xlo > wmax || yhi < 0.0f || ylo > hmax) return true;   // outside the view
-    if (!tiny_cull) return false;
-    return fmaxf(xlo, 0.0f) > fminf(xhi, wmax) || fmaxf(ylo, 0.0f) > fminf(yhi, hmax);
+    const float X = row_dot(R + 0, vx, vy, vz);
+    const float Y = row_dot(R + 4, vx, vy, vz);
+    const float w = row_dot(Aw, vx, vy, vz);
+    const float r = __builtin_amdgcn_rcpf(w);
+    return make_float2(X * r, Y * r);
 }
 
-// Undecided (triangle, draw) pairs wait in a per-wavefront ring in LDS with their exact clip
-// coordinates; the wavefront drains 64 of them at a time with every lane busy.  Head and tail are
-// wave-uniform (scalar), so no workgroup barrier is needed.
-struct RingEntry {
-    float c[9];
+// True when the widened box of three finite window positions provably holds no pixel centre of
+// the view.  The centre of pixel p (an integer in [0, W-1]) is p + 0.5, so a centre lies in
+// [min - m, max + m] iff some integer p in [0, W-1] has lo <= p <= hi, lo = min - m - 0.5,
+// hi = max + m - 0.5.  The largest candidate is min(floor(hi), W-1), so one exists iff
+// f = floor(hi) has f >= 0, f >= lo and lo <= W-1.  Without tiny culling only boxes wholly
+// outside the view (f < 0 or lo > W-1) are rejected.
+__device__ __forceinline__ bool fast_reject_box(float2 a, float2 b, float2 c, const ViewDesc& V, bool tiny_cull)
+{
+    const float lx = fminf(a.x, fminf(b.x, c.x)) - (kFastMargin + 0.5f);
+    const float fx = __builtin_floorf(fmaxf(a.x, fmaxf(b.x, c.x)) + (kFastMargin - 0.5f));
+    const float ly = fminf(a.y, fminf(b.y, c.y)) - (kFastMargin + 0.5f);
+    const float fy = __builtin_floorf(fmaxf(a.y, fmaxf(b.y, c.y)) + (kFastMargin - 0.5f));
+    const bool outside = (fx < 0.0f) | (lx > V.wmax) | (fy < 0.0f) | (ly > V.hmax);
+    const bool empty = (fx < lx) | (fy < ly);
+    return outside | (tiny_cull & empty);
+}
+
+// Same for the output of fast_window, whose x is NaN for a vertex outside the fast range.
+__device__ __forceinline__ bool fast_reject(float2 a, float2 b, float2 c, const ViewDesc& V, bool tiny_cull)
+{
+    if (__builtin_isnan(a.x) | __builtin_isnan(b.x) | __builtin_isnan(c.x)) return false;
+    return fast_reject_box(a, b, c, V, tiny_cull);
+}
+
+// Undecided (triangle, draw) pairs wait in a per-wavefront ring in LDS; the wavefront drains 64 of
+// them at a time with every lane busy, reloading the triangle (rare for dense meshes).  Head and
+// tail are wave-uniform (scalar), so no workgroup barrier is needed.
+struct IdEntry {
     uint32_t draw;
     uint32_t tri;
 };
@@ -416,156 +445,6 @@ __device__ __forceinline__ void wave_lds_sync()
 }
 
 // Exact classification and rasterization of ring entries [head, head + n), n <= 64, one per lane.
-template <bool STATS>
-__device__ __forceinline__ void drain_ring(const RasterArgs& a, const ViewDesc* __restrict__ d_views,
-                                           const DrawDesc* __restrict__ d_draws, const RingEntry* ring,
-                                           uint32_t head, uint32_t n, bool tiny_cull, bool early_out,
-                                           StatAcc<STATS>& st)
-{
-    const uint32_t lane = lane_id();
-    int route = kRouteNone;
-    SmallTri s;
-    uint32_t dd = 0, tt = 0;
-    ViewDesc V;
-    uint64_t idb = 0;
-    if (lane < n) {
-        const RingEntry& e = ring[(head + lane) & (kRing - 1)];
-        dd = e.draw;
-        tt = e.tri;
-        const Clip c[3] = {{e.c[0], e.c[1], e.c[2]}, {e.c[3], e.c[4], e.c[5]}, {e.c[6], e.c[7], e.c[8]}};
-        const DrawDesc& D = d_draws[dd];
-        V = d_views[D.view & kDrawViewMask];
-        idb = D.id_base;
-        route = classify<STATS>(c, V, a.small_px, tiny_cull, s, st);
-    }
-    const unsigned long long slot = wave_reserve(route == kRouteForward, a.counters + kCntQ2);
-    if (route == kRouteForward) {
-        st.add(kStQ2);
-        if (slot < a.q2_cap) {
-            Q2Entry qe;
-            qe.draw = dd;
-            qe.tri = tt;
-            a.q2[slot] = qe;
-        } else {
-            st.add(kStQ2Overflow);
-        }
-    }
-    if (route == kRouteSmall) {
-        st.add(kStS1Raster);
-        raster_small<STATS>(s, idb + tt, V, early_out, st);
-    }
-}
-
-template <int BLOCK, int TPT, bool STATS>
-__global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST_DESC_PARAMS)
-{
-    constexpr int WAVES = BLOCK / 64;
-    __shared__ RingEntry s_ring[WAVES][kRing];
-    const FrameHeader hdr = *d_hdr;
-    uint64_t first, total;
-    work_range(hdr, a.part, first, total);
-    const uint32_t n_segs = uni(hdr.n_segs);
-    const uint32_t dpi = uni(hdr.draws_per_item);
-    const bool early_out = !(a.flags & kFlagNoEarlyOut);
-    const bool tiny_cull = !(a.flags & kFlagNoTinyCull);
-    RingEntry* ring = s_ring[threadIdx.x >> 6];
-    const uint32_t lane = lane_id();
-    uint32_t head = 0, tail = 0;   // wave-uniform
-    StatAcc<STATS> st;
-    for (uint64_t b = first + blockIdx.x; b < total; b += gridDim.x) {
-        const WorkItem wi = locate_work(d_segs, n_segs, dpi, b);
-        const uint64_t tb = wi.tri_batch;
-        const uint32_t d0 = wi.d0, d1 = wi.d1;
-        const MeshDesc mesh = d_meshes[wi.mesh];
-        // issue every index load, then every vertex load, before any use (memory parallelism)
-        uint32_t vi[TPT][3];
-        bool valid[TPT];
-        uint32_t tri[TPT];
-#pragma unroll
-        for (int k = 0; k < TPT; ++k) {
-            const uint64_t t = tb * (uint64_t)(BLOCK * TPT) + (uint64_t)(k * BLOCK) + threadIdx.x;
-            tri[k] = (uint32_t)t;
-            valid[k] = t < mesh.T;
-            const CURAST_GLOBAL uint32_t* ip = gl(mesh.idx) + 3 * (valid[k] ? t : 0);
-            vi[k][0] = ip[0];
-            vi[k][1] = ip[1];
-            vi[k][2] = ip[2];
-        }
-        float p[TPT][9];
-#pragma unroll
-        for (int k = 0; k < TPT; ++k) {
-            valid[k] = valid[k] && vi[k][0] < mesh.V && vi[k][1] < mesh.V && vi[k][2] < mesh.V;
-#pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                const CURAST_GLOBAL float* q = gl(mesh.pos) + 3 * (size_t)(valid[k] ? vi[k][v] : 0);
-                p[k][3 * v + 0] = q[0];
-                p[k][3 * v + 1] = q[1];
-                p[k][3 * v + 2] = q[2];
-            }
-        }
-#pragma unroll 1
-        for (uint32_t d = d0; d < d1; ++d) {
-            const DrawDesc D = d_draws[d];
-            const ViewDesc V = d_views[D.view & kDrawViewMask];
-            const bool interior = (D.view & kDrawInterior) != 0;
-#pragma unroll
-            for (int k = 0; k < TPT; ++k) {
-                const Clip c0 = transform(D.A, p[k][0], p[k][1], p[k][2]);
-                const Clip c1 = transform(D.A, p[k][3], p[k][4], p[k][5]);
-                const Clip c2 = transform(D.A, p[k][6], p[k][7], p[k][8]);
-                bool need = false;
-                if (valid[k]) {
-                    st.add(kStTriDraws);
-                    if (interior)
-                        need = !fast_reject(fast_window_interior(c0, V), fast_window_interior(c1, V),
-                                            fast_window_interior(c2, V), V, tiny_cull);
-                    else
-                        need = !fast_reject(fast_window(c0, V), fast_window(c1, V), fast_window(c2, V), V, tiny_cull);
-                    if (!need) st.add(kStCulledTiny);
-                }
-                const unsigned long long m = __ballot(need);
-                if (m) {
-                    if (need) {
-                        RingEntry& e = ring[(tail + rank_in(m)) & (kRing - 1)];
-                        e.c[0] = c0.x; e.c[1] = c0.y; e.c[2] = c0.w;
-                        e.c[3] = c1.x; e.c[4] = c1.y; e.c[5] = c1.w;
-                        e.c[6] = c2.x; e.c[7] = c2.y; e.c[8] = c2.w;
-                        e.draw = d;
-                        e.tri = tri[k];
-                    }
-                    tail += (uint32_t)__popcll(m);
-                    if (tail - head >= 64) {
-                        wave_lds_sync();
-                        drain_ring<STATS>(a, d_views, d_draws, ring, head, 64, tiny_cull, early_out, st);
-                        head += 64;
-                        wave_lds_sync();
-                    }
-                }
-            }
-        }
-    }
-    if (tail != head) {
-        wave_lds_sync();
-        drain_ring<STATS>(a, d_views, d_draws, ring, head, tail - head, tiny_cull, early_out, st);
-    }
-    (void)lane;
-    st.flush(a.stats);
-}
-
-// ----------------------------------------------------------------------------------------------
-// Stage 1 with vertex sharing, for triangles drawn many times (instances x views).  One wavefront
-// per workgroup: it deduplicates the vertex indices of its 64*TPT triangles in an LDS hash table
-// once per work item, then for every draw transforms each unique vertex once (window positions in
-// LDS) and tests each triangle from those.  The arithmetic of the fast test is the same as in
-// stage1_fast_kernel; undecided (triangle, draw) pairs go through the exact path after reloading
-// the triangle (rare for dense meshes).  Vertex reuse through shared memory is named as future
-// work in the paper's conclusion.
-// ----------------------------------------------------------------------------------------------
-struct IdEntry {
-    uint32_t draw;
-    uint32_t tri;
-};
-
 template <bool STATS>
 __device__ __forceinline__ void drain_ids(const RasterArgs& a, const ViewDesc* __restrict__ d_views,
                                           const MeshDesc* __restrict__ d_meshes, const DrawDesc* __restrict__ d_draws,
@@ -613,6 +492,171 @@ __device__ __forceinline__ void drain_ids(const RasterArgs& a, const ViewDesc* _
     }
 }
 
+// Cyclic rotation of a triangle's three vertex positions so that vertex r comes first (the fast
+// box test does not depend on the order; the exact path reloads the triangle).
+__device__ __forceinline__ void rotate_vertices(float* p, int r)
+{
+    float q[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        // select values, not array elements (a conditional over two lvalues selects addresses,
+        // which would keep the array in scratch memory)
+        const float v0 = p[i], v1 = p[(i + 3) % 9], v2 = p[(i + 6) % 9];
+        q[i] = r == 0 ? v0 : (r == 1 ? v1 : v2);
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) p[i] = q[i];
+}
+
+template <int BLOCK, int TPT, bool PAIRS, bool STATS>
+__global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST_DESC_PARAMS)
+{
+    static_assert(!PAIRS || TPT % 2 == 0, "pairs need an even number of triangles per lane");
+    constexpr int WAVES = BLOCK / 64;
+    constexpr int NP = PAIRS ? TPT / 2 : 1;
+    __shared__ IdEntry s_ring[WAVES][kRing];
+    const FrameHeader hdr = *d_hdr;
+    uint64_t first, total;
+    work_range(hdr, a.part, first, total);
+    const uint32_t n_segs = uni(hdr.n_segs);
+    const uint32_t dpi = uni(hdr.draws_per_item);
+    const bool early_out = !(a.flags & kFlagNoEarlyOut);
+    const bool tiny_cull = !(a.flags & kFlagNoTinyCull);
+    IdEntry* ring = s_ring[threadIdx.x >> 6];
+    uint32_t head = 0, tail = 0;   // wave-uniform
+    StatAcc<STATS> st;
+    for (uint64_t b = first + blockIdx.x; b < total; b += gridDim.x) {
+        const WorkItem wi = locate_work(d_segs, n_segs, dpi, b);
+        const uint64_t tb = wi.tri_batch;
+        const uint32_t d0 = wi.d0, d1 = wi.d1;
+        const MeshDesc mesh = d_meshes[wi.mesh];
+        // issue every index load, then every vertex load, before any use (memory parallelism);
+        // with PAIRS lane l owns triangles TPT l .. TPT l + TPT - 1 of the batch, else l + k BLOCK
+        uint32_t vi[TPT][3];
+        bool valid[TPT];
+        uint32_t tri[TPT];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            const uint64_t t = tb * (uint64_t)(BLOCK * TPT) +
+                               (PAIRS ? (uint64_t)(threadIdx.x * TPT + k) : (uint64_t)(k * BLOCK + threadIdx.x));
+            tri[k] = (uint32_t)t;
+            valid[k] = t < mesh.T;
+            const CURAST_GLOBAL uint32_t* ip = gl(mesh.idx) + 3 * (valid[k] ? t : 0);
+            vi[k][0] = ip[0];
+            vi[k][1] = ip[1];
+            vi[k][2] = ip[2];
+        }
+        float p[TPT][9];
+#pragma unroll
+        for (int k = 0; k < TPT; ++k) {
+            valid[k] = valid[k] && vi[k][0] < mesh.V && vi[k][1] < mesh.V && vi[k][2] < mesh.V;
+#pragma unroll
+            for (int v = 0; v < 3; ++v) {
+                const CURAST_GLOBAL float* q = gl(mesh.pos) + 3 * (size_t)(valid[k] ? vi[k][v] : 0);
+                p[k][3 * v + 0] = q[0];
+                p[k][3 * v + 1] = q[1];
+                p[k][3 * v + 2] = q[2];
+            }
+        }
+        // edge-sharing pairs: the first triangle's vertex missing from the second goes to slot 0,
+        // the second's vertex missing from the first to its slot 0; then the second triangle is
+        // (slot 1, slot 2 of the first, slot 0 of its own) as a set
+        bool pair_ok[NP];
+#pragma unroll
+        for (int j = 0; j < NP; ++j) {
+            pair_ok[j] = false;
+            if constexpr (PAIRS) {
+                const int k0 = 2 * j, k1 = 2 * j + 1;
+                bool in1[3], new1[3];
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    in1[v] = (vi[k0][v] == vi[k1][0]) | (vi[k0][v] == vi[k1][1]) | (vi[k0][v] == vi[k1][2]);
+                    new1[v] = (vi[k1][v] != vi[k0][0]) & (vi[k1][v] != vi[k0][1]) & (vi[k1][v] != vi[k0][2]);
+                }
+                const int n_out = (int)!in1[0] + (int)!in1[1] + (int)!in1[2];
+                const int n_new = (int)new1[0] + (int)new1[1] + (int)new1[2];
+                const bool fits = valid[k0] && n_out == 1 && n_new == 1;
+                pair_ok[j] = __ballot(!valid[k1] || fits) == __ballot(1);
+                rotate_vertices(p[k0], !in1[0] ? 0 : !in1[1] ? 1 : 2);
+                rotate_vertices(p[k1], new1[0] ? 0 : new1[1] ? 1 : 2);
+            }
+        }
+        auto push = [&](bool need, uint32_t d, uint32_t t) {
+            const unsigned long long m = __ballot(need);
+            if (m) {
+                if (need) {
+                    IdEntry e;
+                    e.draw = d;
+                    e.tri = t;
+                    ring[(tail + rank_in(m)) & (kRing - 1)] = e;
+                }
+                tail += (uint32_t)__popcll(m);
+                if (tail - head >= 64) {
+                    wave_lds_sync();
+                    drain_ids<STATS>(a, d_views, d_meshes, d_draws, ring, head, 64, tiny_cull, early_out, st);
+                    head += 64;
+                    wave_lds_sync();
+                }
+            }
+        };
+#pragma unroll 1
+        for (uint32_t d = d0; d < d1; ++d) {
+            const DrawDesc& D = d_draws[d];
+            const ViewDesc V = d_views[D.view & kDrawViewMask];
+            auto body = [&](auto interior_tag) {
+                constexpr bool INTERIOR = decltype(interior_tag)::value;
+                auto win = [&](const float* q) -> float2 {
+                    if constexpr (INTERIOR) return fast_window_prescaled(D.R, D.A + 8, q[0], q[1], q[2]);
+                    else return fast_window(transform(D.A, q[0], q[1], q[2]), V);
+                };
+                auto reject = [&](float2 x, float2 y, float2 z) -> bool {
+                    if constexpr (INTERIOR) return fast_reject_box(x, y, z, V, tiny_cull);
+                    else return fast_reject(x, y, z, V, tiny_cull);
+                };
+                auto decide = [&](int k, bool rejected) {
+                    bool need = false;
+                    if (valid[k]) {
+                        st.add(kStTriDraws);
+                        need = !rejected;
+                        if (rejected) st.add(kStCulledTiny);
+                    }
+                    push(need, d, tri[k]);
+                };
+#pragma unroll
+                for (int j = 0; j < NP; ++j) {
+                    if (PAIRS && pair_ok[j]) {
+                        const int k0 = 2 * j, k1 = 2 * j + 1;
+                        const float2 w0 = win(p[k0] + 0), w1 = win(p[k0] + 3), w2 = win(p[k0] + 6);
+                        const float2 wn = win(p[k1] + 0);
+                        decide(k0, reject(w0, w1, w2));
+                        decide(k1, reject(w1, w2, wn));
+                    } else {
+#pragma unroll
+                        for (int k = PAIRS ? 2 * j : 0; k < (PAIRS ? 2 * j + 2 : TPT); ++k)
+                            decide(k, reject(win(p[k] + 0), win(p[k] + 3), win(p[k] + 6)));
+                    }
+                }
+            };
+            if (D.view & kDrawInterior) body(std::true_type{});
+            else body(std::false_type{});
+        }
+    }
+    if (tail != head) {
+        wave_lds_sync();
+        drain_ids<STATS>(a, d_views, d_meshes, d_draws, ring, head, tail - head, tiny_cull, early_out, st);
+    }
+    st.flush(a.stats);
+}
+
+// ----------------------------------------------------------------------------------------------
+// Stage 1 with vertex sharing, for triangles drawn many times (instances x views).  One wavefront
+// per workgroup: it deduplicates the vertex indices of its 64*TPT triangles in an LDS hash table
+// once per work item, then for every draw transforms each unique vertex once (window positions in
+// LDS) and tests each triangle from those.  The arithmetic of the fast test is the same as in
+// stage1_fast_kernel; undecided (triangle, draw) pairs go through the exact path after reloading
+// the triangle (rare for dense meshes).  Vertex reuse through shared memory is named as future
+// work in the paper's conclusion.
+// ----------------------------------------------------------------------------------------------
 __device__ __forceinline__ uint32_t vertex_hash(uint32_t v, int bits) { return (v * 2654435761u) >> (32 - bits); }
 
 template <int TPT, bool STATS>
@@ -1075,32 +1119,36 @@ hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool
     }
 }
 
-template <int BLOCK, int TPT>
+template <int BLOCK, int TPT, bool PAIRS>
 static hipError_t stage1_fast_dispatch(const RasterArgs& a, bool stats, uint32_t grid, hipStream_t s)
 {
-    if (stats) stage1_fast_kernel<BLOCK, TPT, true><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
-    else stage1_fast_kernel<BLOCK, TPT, false><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    if (stats) stage1_fast_kernel<BLOCK, TPT, PAIRS, true><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    else stage1_fast_kernel<BLOCK, TPT, PAIRS, false><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
     return hipGetLastError();
 }
 
 template <int BLOCK>
-static hipError_t stage1_fast_tpt(const RasterArgs& a, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s)
+static hipError_t stage1_fast_tpt(const RasterArgs& a, uint32_t tpt, bool pairs, bool stats, uint32_t grid,
+                                  hipStream_t s)
 {
     switch (tpt) {
-    case 1: return stage1_fast_dispatch<BLOCK, 1>(a, stats, grid, s);
-    case 2: return stage1_fast_dispatch<BLOCK, 2>(a, stats, grid, s);
-    case 4: return stage1_fast_dispatch<BLOCK, 4>(a, stats, grid, s);
+    case 1: return stage1_fast_dispatch<BLOCK, 1, false>(a, stats, grid, s);
+    case 2: return pairs ? stage1_fast_dispatch<BLOCK, 2, true>(a, stats, grid, s)
+                         : stage1_fast_dispatch<BLOCK, 2, false>(a, stats, grid, s);
+    case 4: return pairs ? stage1_fast_dispatch<BLOCK, 4, true>(a, stats, grid, s)
+                         : stage1_fast_dispatch<BLOCK, 4, false>(a, stats, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s)
+hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool pairs, bool stats, uint32_t grid,
+                              hipStream_t s)
 {
     switch (block) {
-    case 64: return stage1_fast_tpt<64>(a, tpt, stats, grid, s);
-    case 128: return stage1_fast_tpt<128>(a, tpt, stats, grid, s);
-    case 256: return stage1_fast_tpt<256>(a, tpt, stats, grid, s);
-    case 512: return stage1_fast_tpt<512>(a, tpt, stats, grid, s);
+    case 64: return stage1_fast_tpt<64>(a, tpt, pairs, stats, grid, s);
+    case 128: return stage1_fast_tpt<128>(a, tpt, pairs, stats, grid, s);
+    case 256: return stage1_fast_tpt<256>(a, tpt, pairs, stats, grid, s);
+    case 512: return stage1_fast_tpt<512>(a, tpt, pairs, stats, grid, s);
     default: return hipErrorInvalidValue;
     }
 }

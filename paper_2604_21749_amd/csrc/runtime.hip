@@ -24,7 +24,8 @@
 namespace curast {
 hipError_t launch_clear(const RasterArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s);
-hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s);
+hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool pairs, bool stats, uint32_t grid,
+                              hipStream_t s);
 hipError_t launch_stage1_share(const RasterArgs& a, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s);
 hipError_t launch_stage1_overflow(const RasterArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_stage2(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
@@ -124,6 +125,9 @@ int validate_options(const curast_options& o, std::string& msg)
         return bad("s1_block must be 64, 128, 256 or 512");
     if (o.s1_tris_per_thread && o.s1_tris_per_thread != 1 && o.s1_tris_per_thread != 2 && o.s1_tris_per_thread != 4)
         return bad("s1_tris_per_thread must be 1, 2 or 4");
+    if (o.s1_multi_tris_per_thread && o.s1_multi_tris_per_thread != 1 && o.s1_multi_tris_per_thread != 2 &&
+        o.s1_multi_tris_per_thread != 4)
+        return bad("s1_multi_tris_per_thread must be 1, 2 or 4");
     if (o.small_px > 65536) return bad("small_px must be <= 65536");
     if (o.s1_mode > 3) return bad("s1_mode must be 0, 1, 2 or 3");
     if (o.s1_draws_per_item > 65536) return bad("s1_draws_per_item must be <= 65536");
@@ -138,7 +142,8 @@ curast_options resolve_defaults(const curast_options& u, int cus)
     if (!o.small_px) o.small_px = 128;
     if (!o.medium_px) o.medium_px = 4096;
     if (!o.s1_block) o.s1_block = 256;
-    if (!o.s1_tris_per_thread) o.s1_tris_per_thread = 1;
+    if (!o.s1_tris_per_thread) o.s1_tris_per_thread = 4;
+    if (!o.s1_multi_tris_per_thread) o.s1_multi_tris_per_thread = 2;
     if (!o.s1_draws_per_item) o.s1_draws_per_item = 64;
     if (!o.s2_waves) o.s2_waves = (uint32_t)cus * 4;
     if (!o.s3_blocks) o.s3_blocks = (uint32_t)cus * 2;
@@ -322,6 +327,42 @@ bool sphere_interior(const float A[12], const float bs[4], float near_plane)
     return lo > 0.0;
 }
 
+// Prescaled window rows of an interior draw, R = (hW (row x + row w), hH (row y + row w)), rounded
+// once from binary64.  Returns false when the error bound of the fast positions they give (see the
+// stage-1 kernels: hW u ((7 S_x + 19 S_w) / w + 16) against the exact path, plus 2^-9 px of
+// snapping and (3 hW + 1) u of box arithmetic, 1% slack) may exceed the fast margin of 1/32 px
+// anywhere in the bounding sphere; S_r bounds sum_j |row_rj| |v_j| + |row_r3| over the sphere and
+// w is bounded below by its smallest depth.
+bool prescaled_rows(const float A[12], const float bs[4], float hW, float hH, float R[8])
+{
+    const double u = std::ldexp(1.0, -24);
+    const double c[3] = {bs[0], bs[1], bs[2]}, r = bs[3];
+    auto S = [&](int row) {
+        double s = std::fabs((double)A[4 * row + 3]);
+        for (int j = 0; j < 3; ++j) s += std::fabs((double)A[4 * row + j]) * (std::fabs(c[j]) + r);
+        return s;
+    };
+    double w_lo = A[11], g = 0.0, mag = std::fabs((double)A[11]);
+    for (int j = 0; j < 3; ++j) {
+        w_lo += (double)A[8 + j] * c[j];
+        mag += std::fabs((double)A[8 + j] * c[j]);
+        g += (double)A[8 + j] * A[8 + j];
+    }
+    g = std::sqrt(g);
+    w_lo -= r * g + 1e-4 * (mag + r * g);
+    if (!(w_lo > 0.0)) return false;
+    const double sx = S(0), sy = S(1), sw = S(2);
+    auto bound = [&](double h, double s_row) {
+        return 1.01 * (h * u * ((7.0 * s_row + 19.0 * sw) / w_lo + 16.0) + (3.0 * h + 1.0) * u) + std::ldexp(1.0, -9);
+    };
+    if (!(bound(hW, sx) <= 1.0 / 32.0) || !(bound(hH, sy) <= 1.0 / 32.0)) return false;
+    for (int k = 0; k < 4; ++k) {
+        R[k] = (float)((double)hW * ((double)A[k] + (double)A[8 + k]));
+        R[4 + k] = (float)((double)hH * ((double)A[4 + k] + (double)A[8 + k]));
+    }
+    return true;
+}
+
 int check_view(curast_ctx* ctx, const curast_view& v, bool need_vis = true)
 {
     if (v.width < 1 || v.height < 1 || v.width > kMaxDim || v.height > kMaxDim)
@@ -394,13 +435,18 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
         d.hW = 0.5f * (float)views[v].width;
         d.hH = 0.5f * (float)views[v].height;
         d.near_plane = views[v].near_plane;
+        d.wmax = (float)(views[v].width - 1);
+        d.hmax = (float)(views[v].height - 1);
+        d.pad[0] = d.pad[1] = 0;
         d.tile_base = P.hdr.n_tiles;
         P.hdr.n_tiles += (uint32_t)(((d.W + kTileSize - 1) / kTileSize) * ((d.H + kTileSize - 1) / kTileSize));
         P.total_pixels += (uint64_t)d.W * (uint64_t)d.H;
     }
     P.meshes.resize(M);
     uint64_t base = 0;
-    const uint32_t bt_share = 64u * o.s1_tris_per_thread;
+    // triangles per work item of the first stage-1 launch (the vertex-sharing kernel runs 64-lane
+    // workgroups)
+    const uint32_t bt_multi = (o.s1_mode == 3 ? 64u : o.s1_block) * o.s1_multi_tris_per_thread;
     std::vector<uint32_t> mesh_draw_begin(M), mesh_draw_count(M);
     for (uint32_t m = 0; m < M; ++m) {
         const curast_mesh& me = meshes[m];
@@ -422,7 +468,11 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
                 DrawDesc D;
                 draw_matrix(views[v].view_proj, me.instances ? me.instances + 12ull * i : nullptr, D.A);
                 const bool out = cull && sphere_outside(D.A, me.bsphere, views[v].near_plane);
-                const bool inner = !out && sphere_interior(D.A, me.bsphere, views[v].near_plane);
+                for (int k = 0; k < 8; ++k) D.R[k] = 0.0f;
+                const bool inner = !out && !(o.flags & kFlagNoFastInterior) &&
+                                   sphere_interior(D.A, me.bsphere, views[v].near_plane) &&
+                                   prescaled_rows(D.A, me.bsphere, 0.5f * (float)views[v].width,
+                                                  0.5f * (float)views[v].height, D.R);
                 if (visible) visible[(P.pair_count + i) * (uint64_t)n_views + v] = out ? 0 : inner ? 2 : 1;
                 if (out) {
                     P.draws_culled++;
@@ -441,15 +491,12 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
             const uint64_t all = (uint64_t)ni * n_views;
             const uint64_t groups = (all + dpi - 1) / dpi;
             P.max_draws += all;
-            P.max_batches += ((me.num_triangles + std::min(bt, bt_share) - 1) / std::min(bt, bt_share)) * groups;
+            P.max_batches += ((me.num_triangles + std::min(bt, bt_multi) - 1) / std::min(bt, bt_multi)) * groups;
         }
     }
-    // stage-1 segments: meshes drawn several times first (vertex-sharing kernel), then the rest
-    auto shared_mesh = [&](uint32_t m) {
-        if (o.s1_mode == 3) return true;
-        if (o.s1_mode != 0) return false;
-        return mesh_draw_count[m] >= 4;
-    };
+    // stage-1 segments: meshes drawn more than once first (their own launch, whose lanes reuse each
+    // loaded triangle over many draws), then the rest; mode 3 sends every mesh to the first
+    auto shared_mesh = [&](uint32_t m) { return o.s1_mode == 3 || mesh_draw_count[m] >= 2; };
     for (int pass = 0; pass < 2; ++pass) {
         for (uint32_t m = 0; m < M; ++m) {
             const uint32_t dc = mesh_draw_count[m];
@@ -460,7 +507,7 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
             sg.draw_begin = mesh_draw_begin[m];
             sg.draw_count = dc;
             sg.n_groups = (dc + dpi - 1) / dpi;
-            sg.batch_tris = pass == 0 ? bt_share : bt;
+            sg.batch_tris = pass == 0 ? bt_multi : bt;
             P.segs.push_back(sg);
             P.hdr.total_batches += ((meshes[m].num_triangles + sg.batch_tris - 1) / sg.batch_tris) * sg.n_groups;
             P.tri_draws += meshes[m].num_triangles * (uint64_t)dc;
@@ -543,18 +590,24 @@ int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, uint32_t grid_s
     if (e != hipSuccess) return hip_fail(ctx, e, "clear kernel launch");
     if (tf) hipEventRecord(tf->ev[1], s);
     {
-        // work items [0, shared) run the vertex-sharing kernel, the rest the plain one
-        RasterArgs a1 = a;
-        a1.part = 1;
+        // work items [0, shared_batches) are the multi-draw meshes' (part 1), the rest part 2; each
+        // launch's kernel processes s1_block x (its tris-per-thread) triangles per work item,
+        // matching the batch size the plan gave those segments
+        const uint32_t mode = ctx->opt.s1_mode, blk = ctx->opt.s1_block;
+        auto launch_part = [&](uint32_t part, uint32_t tpt, uint32_t grid) {
+            RasterArgs a1 = a;
+            a1.part = part;
+            if (part == 1 && mode == 3) return launch_stage1_share(a1, tpt, stats, grid, s);
+            if (mode == 1) return launch_stage1(a1, blk, tpt, stats, grid, s);
+            const bool pairs = part == 1 && !(ctx->opt.flags & kFlagNoPairs);
+            return launch_stage1_fast(a1, blk, tpt, pairs, stats, grid, s);
+        };
         if (grid_share) {
-            e = launch_stage1_share(a1, ctx->opt.s1_tris_per_thread, stats, grid_share, s);
-            if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 sharing kernel launch");
+            e = launch_part(1, ctx->opt.s1_multi_tris_per_thread, grid_share);
+            if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 kernel launch (multi-draw meshes)");
         }
         if (tf) hipEventRecord(tf->ev[2], s);
-        a1.part = 2;
-        e = ctx->opt.s1_mode == 1
-                ? launch_stage1(a1, ctx->opt.s1_block, ctx->opt.s1_tris_per_thread, stats, std::max<uint32_t>(grid1, 1), s)
-                : launch_stage1_fast(a1, ctx->opt.s1_block, ctx->opt.s1_tris_per_thread, stats, std::max<uint32_t>(grid1, 1), s);
+        e = launch_part(2, ctx->opt.s1_tris_per_thread, std::max<uint32_t>(grid1, 1));
         if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 kernel launch");
     }
     if (tf) hipEventRecord(tf->ev[3], s);
@@ -606,7 +659,8 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
     // options); replays copy the new descriptor contents from the same pinned buffer
     const uint32_t grid1 = grid_for(P.max_batches);
     uint64_t key[8] = {(uint64_t)M, (uint64_t)n_views, (uint64_t)P.max_bytes, (uint64_t)grid1,
-                       ((uint64_t)ctx->opt.s1_block << 32) | ctx->opt.s1_tris_per_thread,
+                       ((uint64_t)ctx->opt.s1_block << 32) | (ctx->opt.s1_tris_per_thread << 8) |
+                           (ctx->opt.s1_multi_tris_per_thread << 4) | ctx->opt.s1_mode,
                        ((uint64_t)ctx->opt.s2_waves << 32) | ctx->opt.s3_blocks,
                        ((uint64_t)ctx->opt.flags << 32) | ctx->opt.small_px,
                        ((uint64_t)ctx->opt.medium_px << 32) | ctx->opt.s1_draws_per_item};

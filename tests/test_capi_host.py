@@ -185,3 +185,20 @@ def test_host_cull_is_conservative(api, seed):
                 assert np.all(P[:, 3] >= view.near) and np.all(ss[:, 2] >= view.near)
                 assert np.all(np.abs(P[:, 0]) <= 2 * P[:, 3]) and np.all(np.abs(P[:, 1]) <= 2 * P[:, 3])
     assert (visible == 2).sum() > 0
+
+
+def test_prescaled_interior_needs_a_small_error_bound(api):
+    """Interior draws take prescaled window rows only when the host's error bound for them is
+    below the fast margin: the same object and camera, with the mesh's coordinates far from its
+    own origin (large matrix terms against a small depth; the sphere stays well inside the
+    frustum), fall back to the general fast path."""
+    pos, idx = W.uv_sphere(6, 12, 1.0)
+    for origin, expect in ((0.0, 2), (100.0, 2), (1e3, 1)):
+        o = np.array([origin, 0.0, origin])
+        p = (pos.astype(np.float64) + o + [0.0, 0.0, -6.0]).astype(np.float32)
+        m = W.Mesh(p, idx, bsphere=W.bounding_sphere(p))
+        view = W.View(W.camera(o, o + [0.0, 0.0, -1.0], aspect=1.0), 0.05, 640, 640)
+        visible, _, _ = api.plan([_cpu_mesh(api, m)], [view])
+        assert visible[0, 0] == expect, (origin, visible)
+        visible, _, _ = api.plan([_cpu_mesh(api, m)], [view], flags=api.FLAG_NO_FAST_INTERIOR)
+        assert visible[0, 0] == 1

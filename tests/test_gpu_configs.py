@@ -118,11 +118,12 @@ def test_c5_resolve_forward_and_backward():
     assert_vis_equal(vis_h, ref_vis, "C5")
     assert np.array_equal(pss_h, O.project(m, view)), "screen positions differ from the oracle"
     assert_resolve_close(out_h, O.resolve_screen(ref_vis, m.idx, 0, pss_h, m.attrs), "C5 resolve")
-    # fp64 reference gradients with the same upstream gradient
-    out64 = O.resolve_screen_f64(ref_vis, m.idx, 0, pss_h, m.attrs)
+    # fp64 reference gradients under the upstream gradient autograd handed to the kernel:
+    # d/d img of sum (img - target)^2 on covered pixels = 2 (img - target), formed in fp32 from the
+    # fp32 image (an fp64 image would move g by ~1e-7 per pixel, which is not the kernel's error)
     cov = ref_vis != O.EMPTY
-    gout = np.where(cov[..., None], 2.0 * (out64 - target), 0.0)
-    ra, rp = O.resolve_screen_backward_f64(ref_vis, m.idx, 0, pss_h, m.attrs, gout)
+    g32 = np.where(cov[..., None], np.float32(2.0) * (out_h - target.astype(np.float32)), np.float32(0.0))
+    ra, rp = O.resolve_screen_backward_f64(ref_vis, m.idx, 0, pss_h, m.attrs, g32.astype(np.float64))
     sa = np.maximum(np.abs(ra), 1e-3 * np.sqrt(np.mean(ra ** 2)))
     assert np.all(np.abs(ga - ra) <= 1e-3 * sa), f"attribute gradient: {np.max(np.abs(ga - ra) / sa)}"
     sp = np.maximum(np.abs(rp), 1e-3 * np.sqrt(np.mean(rp ** 2)))

@@ -89,6 +89,7 @@ OPTION_SWEEP = [
     dict(s1_mode=3, s1_tris_per_thread=1), dict(s1_mode=3, s1_tris_per_thread=4, flags=api.FLAG_ZERO_QUEUES),
     dict(flags=api.FLAG_S3_PER_PART), dict(flags=api.FLAG_S3_PER_PART, medium_px=1),
     dict(medium_px=1, s3_blocks=3), dict(medium_px=64, q3_capacity=7),
+    dict(s1_multi_tris_per_thread=4, s1_tris_per_thread=1), dict(s1_multi_tris_per_thread=1, s1_block=512),
 ]
 
 
@@ -106,10 +107,11 @@ def test_options_do_not_change_results(opts):
             assert_vis_equal(api.as_uint64(v2), O.rasterize(t.meshes, t.views[0]), f"tiny {seed} with {opts}")
 
 
-@pytest.mark.parametrize("mode", [0, 1, 2, 3])
-def test_instanced_stage1_modes(mode):
-    """Instanced meshes go through the vertex-sharing path (LDS deduplication) in modes 0 and 3."""
-    with api.Context(s1_mode=mode, s1_draws_per_item=8) as c:
+@pytest.mark.parametrize("mode,tpt", [(0, 2), (0, 1), (0, 4), (1, 2), (2, 4), (3, 1), (3, 2), (3, 4)])
+def test_instanced_stage1_modes(mode, tpt):
+    """Instanced meshes take the first stage-1 launch (the vertex-sharing kernel with LDS
+    deduplication in mode 3), at every multi-draw batch size."""
+    with api.Context(s1_mode=mode, s1_draws_per_item=8, s1_multi_tris_per_thread=tpt) as c:
         for seed in range(6):
             s = W.random_tiny_scene(seed, n_instances=13, n_tris=40, spread=3.0)
             # shared vertices: rebuild the index buffer over a small vertex pool
@@ -162,3 +164,49 @@ def test_stats_account_for_every_triangle(mode):
     assert st["tri_draws"] == 262146
     assert done == st["tri_draws"], st
     assert st["q2_entries"] >= 2 and st["q3_entries"] > 0 and st["fragments"] > 0
+
+
+def _edge_pair_scene(seed):
+    """Instanced meshes whose consecutive triangles share edges (UV sphere, unshuffled height-field
+    patch), a copy with a few triangles moved out of order, degenerate duplicates and an odd
+    count, drawn near and far, inside the frustum and across its sides and near plane."""
+    rng = np.random.default_rng(seed)
+    pos, idx = W.uv_sphere(24, 48, 1.0)
+    hpos, hidx = W.heightfield(33, 0.15, 5 + seed, shuffle=False)
+    hpos = hpos - np.array([0.5, 0.0, 0.5], np.float32)
+    broken = idx.copy()
+    moved = rng.choice(len(broken), len(broken) // 30, replace=False)
+    broken[np.sort(moved)] = broken[moved]
+    broken[rng.choice(len(broken), 7, replace=False), 1] = broken[rng.choice(len(broken), 7, replace=False), 0]
+    broken = broken[:-1]
+    n = 14
+    R = W.random_rotations(rng, n)
+    t = np.stack([rng.uniform(-6, 6, n), rng.uniform(-4, 4, n), -rng.uniform(2.5, 30, n)], 1)
+    t[0] = (0.0, 0.0, -0.6)          # straddles the near plane
+    t[1] = (9.0, 0.0, -8.0)          # straddles the frustum side
+    inst = W.instance_matrices(R, rng.uniform(0.5, 2.0, n), t)
+    meshes = [W.Mesh(pos, idx, inst=inst, bsphere=W.bounding_sphere(pos)),
+              W.Mesh(hpos, hidx, inst=inst[::-1].copy(), bsphere=W.bounding_sphere(hpos)),
+              W.Mesh(pos, broken, inst=inst[3:].copy(), bsphere=W.bounding_sphere(pos))]
+    vp = W.camera((0.0, 0.0, 0.0), (0.0, 0.0, -1.0), aspect=256 / 192)
+    return W.Scene(f"pairs_{seed}", meshes, [W.View(vp, 0.05, 256, 192)])
+
+
+@pytest.mark.parametrize("opts", [
+    {}, dict(flags=api.FLAG_NO_PAIRS), dict(flags=api.FLAG_NO_FAST_INTERIOR),
+    dict(flags=api.FLAG_NO_PAIRS | api.FLAG_NO_FAST_INTERIOR), dict(s1_multi_tris_per_thread=4),
+    dict(s1_multi_tris_per_thread=4, s1_block=64), dict(s1_multi_tris_per_thread=2, s1_block=512),
+    dict(flags=api.FLAG_NO_TINY_CULL), dict(s1_mode=2, small_px=1, medium_px=1),
+])
+def test_edge_sharing_pairs_and_interior_draws(opts):
+    """The pair path (four window positions per edge-sharing triangle pair) and the prescaled
+    interior rows reject only what the exact path would: bit-identical to the oracle."""
+    with api.Context(**opts) as c:
+        for seed in range(3):
+            s = _edge_pair_scene(seed)
+            gm = gpu_meshes(s)
+            visible, _, counts = api.plan(gm, s.views)
+            if not (opts.get("flags", 0) & api.FLAG_NO_FAST_INTERIOR):
+                assert (visible == 2).sum() > 5, counts
+            vis = c.rasterize_meshes(gm, s.views[0])
+            assert_vis_equal(api.as_uint64(vis), O.rasterize(s.meshes, s.views[0]), f"pairs seed {seed} {opts}")
