@@ -30,11 +30,11 @@ METRIC = "Gtris/s & ms/frame at 3840x2160 (plain vs batched); resolve bwd ms"
 HBM_PEAK_GBS = 8000.0
 # VALU peak without packed fp32: 256 CUs x 64 lanes x 2.4 GHz (lane-operations per second)
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-# algorithmic lane-operations of the fast reject per triangle instance of a mesh with V/T = 1/2:
-# per vertex and draw 9 FMA (transform) + 1 reciprocal + 2 MUL + 2 FMA (window position) = 14,
-# half a vertex per triangle; per triangle 4 min/max, 4 margin adds, 4 floor/ceil, 4 clamps and
-# 3 compares = 19
-ALU_OPS_PER_TRI_INST = 14 * 0.5 + 19
+# algorithmic lane-operations of the brute-force fast reject per triangle instance of a closed mesh
+# (V/T = 1/2): each vertex projected once per draw (three 4-term dot products = 9 FMA, one
+# reciprocal, two multiplies = 12) and one box test per triangle (4 min/max, 4 margin adds,
+# 2 floors, 6 compares = 16)
+ALU_OPS_PER_TRI_INST = 12 * 0.5 + 16
 
 
 def log(*a):
@@ -137,8 +137,9 @@ def stage1_rooflines(h):
     algorithmic lane-operations = ALU_OPS_PER_TRI_INST per triangle instance."""
     sm = h["stage_ms"]
     o = h["options"]
-    k_single = f"stage1_fast_kernel<{o['s1_block']},{o['s1_tris_per_thread']}>"
-    k_multi = f"stage1_fast_kernel<{o['s1_block']},{o['s1_multi_tris_per_thread']}>"
+    strips = "true" if (o["s1_multi_tris_per_thread"] in (2, 4) and not (o["flags"] & 0x100)) else "false"
+    k_single = f"stage1_fast_kernel<{o['s1_block']}, {o['s1_tris_per_thread']}, false, false>"
+    k_multi = f"stage1_fast_kernel<{o['s1_block']}, {o['s1_multi_tris_per_thread']}, {strips}, false>"
     single_bytes = stage1_algorithmic_bytes(h["single"])
     single_ach = single_bytes / max(sm["stage1_single"] * 1e-3, 1e-12) / 1e9
     tri_inst = int(sum(m.num_triangles * m.num_instances for m in h["multi"]))

@@ -78,9 +78,11 @@ typedef enum {
                                            the default one workgroup per binned screen tile */
 #define CURAST_FLAG_NO_FAST_INTERIOR 0x80u /* stage 1: no prescaled window rows for draws whose
                                                 bounding sphere lies well inside the view frustum */
-#define CURAST_FLAG_NO_PAIRS      0x100u /* stage 1, meshes with several draws: no edge-sharing
-                                            triangle pairs (each triangle takes three window
+#define CURAST_FLAG_NO_STRIPS     0x100u /* stage 1, meshes with several draws: do not detect
+                                            triangle strips (each triangle then takes three window
                                             positions per draw) */
+#define CURAST_FLAG_SINGLE_STRIPS 0x200u /* stage 1: detect triangle strips in the launch over
+                                            single-draw meshes too */
 #define CURAST_FLAG_ZERO_QUEUES   0x80000000u /* testing aid: run with stage queues of capacity 0, so
                                                  every forwarded triangle takes the overflow paths */
 
@@ -88,7 +90,7 @@ typedef enum {
 typedef struct {
     uint32_t small_px;          /* stage-1 limit on pixel centres in the clamped bbox (default 128, Sec. 4) */
     uint32_t medium_px;         /* stage-2 limit (default 4096, Sec. 4) */
-    uint32_t s1_block;          /* stage-1 workgroup size: 64, 128, 256 or 512 (default 256, Sec. 4.1) */
+    uint32_t s1_block;          /* stage-1 workgroup size: 64, 128, 256 or 512 (default 128, Sec. 4.1) */
     uint32_t s1_tris_per_thread;/* triangles per thread per stage-1 work item of a mesh drawn once:
                                    1, 2 or 4 (default 4) */
     uint32_t s1_draws_per_item; /* (instance x view) draws per stage-1 work item (default 64, Sec. 4.5) */
@@ -106,7 +108,7 @@ typedef struct {
                                    (each vertex transformed once per wave and draw) */
     uint32_t s1_multi_tris_per_thread; /* as s1_tris_per_thread, for meshes with two or more
                                    surviving draws, which stage 1 takes in a launch of its own
-                                   (default 2) */
+                                   (default 4) */
 } curast_options;
 
 typedef struct {

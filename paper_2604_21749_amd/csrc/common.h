@@ -117,7 +117,8 @@ constexpr uint32_t kFlagStats = 0x8u;
 constexpr uint32_t kFlagNoGraph = 0x10u;
 constexpr uint32_t kFlagS3PerPart = 0x40u;          // stage 3 per tile part instead of per binned tile
 constexpr uint32_t kFlagNoFastInterior = 0x80u;     // no prescaled interior draws in stage 1
-constexpr uint32_t kFlagNoPairs = 0x100u;           // no edge-sharing pairs in stage 1
+constexpr uint32_t kFlagNoStrips = 0x100u;          // no triangle strips in stage 1
+constexpr uint32_t kFlagSingleStrips = 0x200u;      // strips in the single-draw stage-1 launch too
 constexpr uint32_t kFlagZeroQueues = 0x80000000u;   // testing aid: queue capacities of zero
 
 struct RasterArgs {

@@ -360,9 +360,10 @@ __global__ void __launch_bounds__(BLOCK) stage1_kernel(RasterArgs a, CURAST_DESC
 //  (3) interior draws (bounding sphere inside |x|, |y| <= 1.99 w, w >= 1.001 near, checked on the
 //      host) skip the per-vertex range tests and take their window position from two prescaled
 //      rows, x'' = hW (row x + row w) . (v, 1) and likewise y'', so that x''/w is the window x;
-//  (4) with PAIRS a lane owns consecutive triangles; when every lane's second triangle shares an
-//      edge with its first (one vertex of each outside the other), the pair needs four window
-//      positions instead of six.
+//  (4) with STRIPS a lane owns TPT consecutive triangles; when every lane's triangles form a
+//      strip (each shares an edge with the next, as along the rows of a grid or the bands of a
+//      sphere) they need TPT + 2 window positions per draw instead of 3 TPT, and one test of the
+//      box around all of them rejects the whole strip (it contains each triangle's box).
 //
 // Error bounds (u = 2^-24; S_r = sum_j |row_rj| |v_j| + |row_r3| over the vertex, w its depth):
 //  exact path: x and w carry at most 3u S_x and 3u S_w of fma-chain error, and 1/w, x*zI and the
@@ -404,21 +405,28 @@ __device__ __forceinline__ float2 fast_window_prescaled(const float* R, const fl
     return make_float2(X * r, Y * r);
 }
 
-// True when the widened box of three finite window positions provably holds no pixel centre of
-// the view.  The centre of pixel p (an integer in [0, W-1]) is p + 0.5, so a centre lies in
-// [min - m, max + m] iff some integer p in [0, W-1] has lo <= p <= hi, lo = min - m - 0.5,
-// hi = max + m - 0.5.  The largest candidate is min(floor(hi), W-1), so one exists iff
-// f = floor(hi) has f >= 0, f >= lo and lo <= W-1.  Without tiny culling only boxes wholly
-// outside the view (f < 0 or lo > W-1) are rejected.
-__device__ __forceinline__ bool fast_reject_box(float2 a, float2 b, float2 c, const ViewDesc& V, bool tiny_cull)
+// True when the widened extent [xmin, xmax] x [ymin, ymax] of finite window positions provably
+// holds no pixel centre of the view.  The centre of pixel p (an integer in [0, W-1]) is p + 0.5,
+// so a centre lies in [min - m, max + m] iff some integer p in [0, W-1] has lo <= p <= hi,
+// lo = min - m - 0.5, hi = max + m - 0.5.  The largest candidate is min(floor(hi), W-1), so one
+// exists iff f = floor(hi) has f >= 0, f >= lo and lo <= W-1.  Without tiny culling only boxes
+// wholly outside the view (f < 0 or lo > W-1) are rejected.
+__device__ __forceinline__ bool fast_reject_extent(float xmin, float xmax, float ymin, float ymax, const ViewDesc& V,
+                                                   bool tiny_cull)
 {
-    const float lx = fminf(a.x, fminf(b.x, c.x)) - (kFastMargin + 0.5f);
-    const float fx = __builtin_floorf(fmaxf(a.x, fmaxf(b.x, c.x)) + (kFastMargin - 0.5f));
-    const float ly = fminf(a.y, fminf(b.y, c.y)) - (kFastMargin + 0.5f);
-    const float fy = __builtin_floorf(fmaxf(a.y, fmaxf(b.y, c.y)) + (kFastMargin - 0.5f));
+    const float lx = xmin - (kFastMargin + 0.5f);
+    const float fx = __builtin_floorf(xmax + (kFastMargin - 0.5f));
+    const float ly = ymin - (kFastMargin + 0.5f);
+    const float fy = __builtin_floorf(ymax + (kFastMargin - 0.5f));
     const bool outside = (fx < 0.0f) | (lx > V.wmax) | (fy < 0.0f) | (ly > V.hmax);
     const bool empty = (fx < lx) | (fy < ly);
     return outside | (tiny_cull & empty);
+}
+
+__device__ __forceinline__ bool fast_reject_box(float2 a, float2 b, float2 c, const ViewDesc& V, bool tiny_cull)
+{
+    return fast_reject_extent(fminf(a.x, fminf(b.x, c.x)), fmaxf(a.x, fmaxf(b.x, c.x)), fminf(a.y, fminf(b.y, c.y)),
+                              fmaxf(a.y, fmaxf(b.y, c.y)), V, tiny_cull);
 }
 
 // Same for the output of fast_window, whose x is NaN for a vertex outside the fast range.
@@ -429,11 +437,19 @@ __device__ __forceinline__ bool fast_reject(float2 a, float2 b, float2 c, const 
 }
 
 // Undecided (triangle, draw) pairs wait in a per-wavefront ring in LDS; the wavefront drains 64 of
-// them at a time with every lane busy, reloading the triangle (rare for dense meshes).  Head and
+// them at a time with every lane busy.  Entries carry the exact clip coordinates where the lane
+// has them at hand (ClipEntry: the drain then loads only the draw and its view); the strip
+// kernels store ids (IdEntry) and the drain reloads the triangle, which is rare there.  Head and
 // tail are wave-uniform (scalar), so no workgroup barrier is needed.
+struct ClipEntry {
+    float c[9];
+    uint32_t draw;
+    uint32_t tri;
+};
 struct IdEntry {
     uint32_t draw;
     uint32_t tri;
+    uint32_t mesh;
 };
 constexpr int kRing = 128;
 
@@ -444,36 +460,16 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Exact classification and rasterization of ring entries [head, head + n), n <= 64, one per lane.
+// Exact classification of one (draw, triangle) per lane with `have`, then Q2 or the small
+// rasterizer.  Every lane of the wavefront takes part (the Q2 reservation is wave-wide).
 template <bool STATS>
-__device__ __forceinline__ void drain_ids(const RasterArgs& a, const ViewDesc* __restrict__ d_views,
-                                          const MeshDesc* __restrict__ d_meshes, const DrawDesc* __restrict__ d_draws,
-                                          const IdEntry* ring, uint32_t head, uint32_t n, bool tiny_cull,
-                                          bool early_out, StatAcc<STATS>& st)
+__device__ __forceinline__ void exact_route(const RasterArgs& a, bool have, const Clip (&c)[3], const ViewDesc& V,
+                                            uint32_t dd, uint32_t tt, uint64_t idb, bool tiny_cull, bool early_out,
+                                            StatAcc<STATS>& st)
 {
-    const uint32_t lane = lane_id();
     int route = kRouteNone;
     SmallTri s;
-    uint32_t dd = 0, tt = 0;
-    ViewDesc V;
-    uint64_t idb = 0;
-    if (lane < n) {
-        const IdEntry e = ring[(head + lane) & (kRing - 1)];
-        dd = e.draw;
-        tt = e.tri;
-        const DrawDesc& D = d_draws[dd];
-        V = d_views[D.view & kDrawViewMask];
-        idb = D.id_base;
-        const MeshDesc& M = d_meshes[D.mesh];
-        const CURAST_GLOBAL uint32_t* ip = gl(M.idx) + 3 * (uint64_t)tt;
-        Clip c[3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const CURAST_GLOBAL float* q = gl(M.pos) + 3 * (size_t)ip[k];
-            c[k] = transform(D.A, q[0], q[1], q[2]);
-        }
-        route = classify<STATS>(c, V, a.small_px, tiny_cull, s, st);
-    }
+    if (have) route = classify<STATS>(c, V, a.small_px, tiny_cull, s, st);
     const unsigned long long slot = wave_reserve(route == kRouteForward, a.counters + kCntQ2);
     if (route == kRouteForward) {
         st.add(kStQ2);
@@ -492,29 +488,128 @@ __device__ __forceinline__ void drain_ids(const RasterArgs& a, const ViewDesc* _
     }
 }
 
-// Cyclic rotation of a triangle's three vertex positions so that vertex r comes first (the fast
-// box test does not depend on the order; the exact path reloads the triangle).
-__device__ __forceinline__ void rotate_vertices(float* p, int r)
+// Drain ring entries [head, head + n), n <= 64, one per lane.
+template <bool STATS>
+__device__ __forceinline__ void drain_ring(const RasterArgs& a, const ViewDesc* __restrict__ d_views,
+                                           const MeshDesc* __restrict__, const DrawDesc* __restrict__ d_draws,
+                                           const ClipEntry* ring, uint32_t head, uint32_t n, bool tiny_cull,
+                                           bool early_out, StatAcc<STATS>& st)
 {
-    float q[9];
+    const bool have = lane_id() < n;
+    Clip c[3] = {};
+    ViewDesc V;
+    uint32_t dd = 0, tt = 0;
+    uint64_t idb = 0;
+    if (have) {
+        const ClipEntry& e = ring[(head + lane_id()) & (kRing - 1)];
+        dd = e.draw;
+        tt = e.tri;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        // select values, not array elements (a conditional over two lvalues selects addresses,
-        // which would keep the array in scratch memory)
-        const float v0 = p[i], v1 = p[(i + 3) % 9], v2 = p[(i + 6) % 9];
-        q[i] = r == 0 ? v0 : (r == 1 ? v1 : v2);
+        for (int k = 0; k < 3; ++k) c[k] = Clip{e.c[3 * k], e.c[3 * k + 1], e.c[3 * k + 2]};
+        const DrawDesc& D = d_draws[dd];
+        V = d_views[D.view & kDrawViewMask];
+        idb = D.id_base;
     }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) p[i] = q[i];
+    exact_route<STATS>(a, have, c, V, dd, tt, idb, tiny_cull, early_out, st);
 }
 
-template <int BLOCK, int TPT, bool PAIRS, bool STATS>
+template <bool STATS>
+__device__ __forceinline__ void drain_ring(const RasterArgs& a, const ViewDesc* __restrict__ d_views,
+                                           const MeshDesc* __restrict__ d_meshes, const DrawDesc* __restrict__ d_draws,
+                                           const IdEntry* ring, uint32_t head, uint32_t n, bool tiny_cull,
+                                           bool early_out, StatAcc<STATS>& st)
+{
+    const bool have = lane_id() < n;
+    Clip c[3] = {};
+    ViewDesc V;
+    uint32_t dd = 0, tt = 0;
+    uint64_t idb = 0;
+    if (have) {
+        const IdEntry e = ring[(head + lane_id()) & (kRing - 1)];
+        dd = e.draw;
+        tt = e.tri;
+        const DrawDesc& D = d_draws[dd];
+        const MeshDesc& M = d_meshes[e.mesh];
+        const CURAST_GLOBAL uint32_t* ip = gl(M.idx) + 3 * (uint64_t)tt;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const CURAST_GLOBAL float* q = gl(M.pos) + 3 * (size_t)ip[k];
+            c[k] = transform(D.A, q[0], q[1], q[2]);
+        }
+        V = d_views[D.view & kDrawViewMask];
+        idb = D.id_base;
+    }
+    exact_route<STATS>(a, have, c, V, dd, tt, idb, tiny_cull, early_out, st);
+}
+
+// The vertex of triangle a missing from triangle b; true when exactly one is.
+__device__ __forceinline__ bool one_missing(const uint32_t (&a)[3], const uint32_t (&b)[3], uint32_t& out)
+{
+    bool m[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m[j] = (a[j] != b[0]) & (a[j] != b[1]) & (a[j] != b[2]);
+    out = m[0] ? a[0] : (m[1] ? a[1] : a[2]);
+    return (int)m[0] + (int)m[1] + (int)m[2] == 1;
+}
+
+__device__ __forceinline__ bool in_tri(uint32_t v, const uint32_t (&t)[3]) { return (v == t[0]) | (v == t[1]) | (v == t[2]); }
+
+// Vertex sequence v[0..S+1] with triangle k = {v[k], v[k+1], v[k+2]} as a set, for S consecutive
+// triangles each sharing an edge with the next (a strip: rows of a grid, bands of a sphere).
+// Returns false when the triangles do not form one; v is then unspecified.
+template <int S>
+__device__ __forceinline__ bool build_strip(const uint32_t (&t)[S][3], uint32_t (&v)[S + 2])
+{
+    static_assert(S == 2 || S == 4, "strips of 2 or 4 triangles");
+    bool ok = true;
+    uint32_t out[S], nw[S];
+#pragma unroll
+    for (int k = 0; k + 1 < S; ++k) ok &= one_missing(t[k], t[k + 1], out[k]);
+#pragma unroll
+    for (int k = 1; k < S; ++k) ok &= one_missing(t[k], t[k - 1], nw[k]);
+    if constexpr (S == 2) {
+        v[0] = out[0];
+        v[1] = out[0] == t[0][0] ? t[0][1] : (out[0] == t[0][1] ? t[0][2] : t[0][0]);
+        v[2] = out[0] == t[0][0] ? t[0][2] : (out[0] == t[0][1] ? t[0][0] : t[0][1]);
+        v[3] = nw[1];
+    } else {
+        v[0] = out[0];
+        v[1] = out[1];
+        v[2] = out[2];
+        v[3] = nw[1];
+        v[4] = nw[2];
+        v[5] = nw[3];
+    }
+    // every triangle is exactly its three sequence vertices, all distinct
+#pragma unroll
+    for (int k = 0; k < S; ++k)
+        ok &= in_tri(v[k], t[k]) & in_tri(v[k + 1], t[k]) & in_tri(v[k + 2], t[k]) & (v[k] != v[k + 1]) &
+              (v[k] != v[k + 2]) & (v[k + 1] != v[k + 2]);
+    return ok;
+}
+
+// The same test on the union box of N finite window positions.
+template <int N>
+__device__ __forceinline__ bool fast_reject_union(const float2 (&w)[N], const ViewDesc& V, bool tiny_cull)
+{
+    float x0 = w[0].x, x1 = w[0].x, y0 = w[0].y, y1 = w[0].y;
+#pragma unroll
+    for (int i = 1; i < N; ++i) {
+        x0 = fminf(x0, w[i].x);
+        x1 = fmaxf(x1, w[i].x);
+        y0 = fminf(y0, w[i].y);
+        y1 = fmaxf(y1, w[i].y);
+    }
+    return fast_reject_extent(x0, x1, y0, y1, V, tiny_cull);
+}
+
+template <int BLOCK, int TPT, bool STRIPS, bool STATS>
 __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST_DESC_PARAMS)
 {
-    static_assert(!PAIRS || TPT % 2 == 0, "pairs need an even number of triangles per lane");
+    static_assert(!STRIPS || TPT == 2 || TPT == 4, "strips of 2 or 4 triangles per lane");
     constexpr int WAVES = BLOCK / 64;
-    constexpr int NP = PAIRS ? TPT / 2 : 1;
-    __shared__ IdEntry s_ring[WAVES][kRing];
+    using Entry = typename std::conditional<STRIPS, IdEntry, ClipEntry>::type;
+    __shared__ Entry s_ring[WAVES][kRing];
     const FrameHeader hdr = *d_hdr;
     uint64_t first, total;
     work_range(hdr, a.part, first, total);
@@ -522,23 +617,58 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
     const uint32_t dpi = uni(hdr.draws_per_item);
     const bool early_out = !(a.flags & kFlagNoEarlyOut);
     const bool tiny_cull = !(a.flags & kFlagNoTinyCull);
-    IdEntry* ring = s_ring[threadIdx.x >> 6];
+    Entry* ring = s_ring[threadIdx.x >> 6];
     uint32_t head = 0, tail = 0;   // wave-uniform
     StatAcc<STATS> st;
+    // append (draw d, triangle t) where `need`; fill(e) writes the rest of the entry
+    auto push = [&](bool need, uint32_t d, uint32_t t, auto&& fill) {
+        const unsigned long long m = __ballot(need);
+        if (m) {
+            if (need) {
+                Entry& e = ring[(tail + rank_in(m)) & (kRing - 1)];
+                e.draw = d;
+                e.tri = t;
+                fill(e);
+            }
+            tail += (uint32_t)__popcll(m);
+            if (tail - head >= 64) {
+                wave_lds_sync();
+                drain_ring<STATS>(a, d_views, d_meshes, d_draws, ring, head, 64, tiny_cull, early_out, st);
+                head += 64;
+                wave_lds_sync();
+            }
+        }
+    };
+    auto count = [&](bool valid, bool rejected) {
+        if (valid) {
+            st.add(kStTriDraws);
+            if (rejected) st.add(kStCulledTiny);
+        }
+    };
+    // window position of one vertex and the per-triangle test, for interior draws (prescaled rows,
+    // no range tests) or general ones (exact transform, range tests, NaN for an undecidable vertex)
+    auto window = [&](auto interior_tag, const DrawDesc& D, const ViewDesc& V, const float* q) -> float2 {
+        if constexpr (decltype(interior_tag)::value) return fast_window_prescaled(D.R, D.A + 8, q[0], q[1], q[2]);
+        else return fast_window(transform(D.A, q[0], q[1], q[2]), V);
+    };
+    auto reject = [&](auto interior_tag, float2 x, float2 y, float2 z, const ViewDesc& V) -> bool {
+        if constexpr (decltype(interior_tag)::value) return fast_reject_box(x, y, z, V, tiny_cull);
+        else return fast_reject(x, y, z, V, tiny_cull);
+    };
     for (uint64_t b = first + blockIdx.x; b < total; b += gridDim.x) {
         const WorkItem wi = locate_work(d_segs, n_segs, dpi, b);
         const uint64_t tb = wi.tri_batch;
         const uint32_t d0 = wi.d0, d1 = wi.d1;
         const MeshDesc mesh = d_meshes[wi.mesh];
-        // issue every index load, then every vertex load, before any use (memory parallelism);
-        // with PAIRS lane l owns triangles TPT l .. TPT l + TPT - 1 of the batch, else l + k BLOCK
+        // issue every index load before any use (memory parallelism); with STRIPS lane l owns
+        // triangles TPT l .. TPT l + TPT - 1 of the batch, else l + k BLOCK
         uint32_t vi[TPT][3];
         bool valid[TPT];
         uint32_t tri[TPT];
 #pragma unroll
         for (int k = 0; k < TPT; ++k) {
             const uint64_t t = tb * (uint64_t)(BLOCK * TPT) +
-                               (PAIRS ? (uint64_t)(threadIdx.x * TPT + k) : (uint64_t)(k * BLOCK + threadIdx.x));
+                               (STRIPS ? (uint64_t)(threadIdx.x * TPT + k) : (uint64_t)(k * BLOCK + threadIdx.x));
             tri[k] = (uint32_t)t;
             valid[k] = t < mesh.T;
             const CURAST_GLOBAL uint32_t* ip = gl(mesh.idx) + 3 * (valid[k] ? t : 0);
@@ -546,104 +676,157 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
             vi[k][1] = ip[1];
             vi[k][2] = ip[2];
         }
-        float p[TPT][9];
 #pragma unroll
-        for (int k = 0; k < TPT; ++k) {
+        for (int k = 0; k < TPT; ++k)
             valid[k] = valid[k] && vi[k][0] < mesh.V && vi[k][1] < mesh.V && vi[k][2] < mesh.V;
+        if constexpr (STRIPS) {
+            auto fill_id = [&](IdEntry& e) { e.mesh = wi.mesh; };
+            // strip mode when every lane with a valid triangle has TPT valid triangles forming a
+            // strip: TPT + 2 window positions per draw, and one test of their union box rejects
+            // all TPT triangles at once (it holds each triangle's box)
+            uint32_t sv[TPT + 2];
+            bool all_valid = true, any_valid = false;
 #pragma unroll
-            for (int v = 0; v < 3; ++v) {
-                const CURAST_GLOBAL float* q = gl(mesh.pos) + 3 * (size_t)(valid[k] ? vi[k][v] : 0);
-                p[k][3 * v + 0] = q[0];
-                p[k][3 * v + 1] = q[1];
-                p[k][3 * v + 2] = q[2];
+            for (int k = 0; k < TPT; ++k) {
+                all_valid &= valid[k];
+                any_valid |= valid[k];
             }
-        }
-        // edge-sharing pairs: the first triangle's vertex missing from the second goes to slot 0,
-        // the second's vertex missing from the first to its slot 0; then the second triangle is
-        // (slot 1, slot 2 of the first, slot 0 of its own) as a set
-        bool pair_ok[NP];
+            const bool lane_strip = build_strip<TPT>(vi, sv) && all_valid;
+            if (__ballot(!any_valid || lane_strip) == __ballot(1)) {
+                float q[TPT + 2][3];
 #pragma unroll
-        for (int j = 0; j < NP; ++j) {
-            pair_ok[j] = false;
-            if constexpr (PAIRS) {
-                const int k0 = 2 * j, k1 = 2 * j + 1;
-                bool in1[3], new1[3];
+                for (int i = 0; i < TPT + 2; ++i) {
+                    const CURAST_GLOBAL float* src = gl(mesh.pos) + 3 * (size_t)(any_valid ? sv[i] : 0u);
+                    q[i][0] = src[0];
+                    q[i][1] = src[1];
+                    q[i][2] = src[2];
+                }
+#pragma unroll 1
+                for (uint32_t d = d0; d < d1; ++d) {
+                    const DrawDesc& D = d_draws[d];
+                    const ViewDesc V = d_views[D.view & kDrawViewMask];
+                    auto body = [&](auto tag) {
+                        constexpr bool INTERIOR = decltype(tag)::value;
+                        float2 w[TPT + 2];
+                        bool any_nan = false;
+#pragma unroll
+                        for (int i = 0; i < TPT + 2; ++i) {
+                            w[i] = window(tag, D, V, q[i]);
+                            if constexpr (!INTERIOR) any_nan |= __builtin_isnan(w[i].x);
+                        }
+                        const bool all_out = !any_nan && fast_reject_union<TPT + 2>(w, V, tiny_cull);
+                        if (any_valid) {
+                            st.add(kStTriDraws, TPT);
+                            if (all_out) st.add(kStCulledTiny, TPT);
+                        }
+                        const bool pass = any_valid && !all_out;
+                        if (__ballot(pass)) {
+#pragma unroll
+                            for (int k = 0; k < TPT; ++k) {
+                                const bool rej = reject(tag, w[k], w[k + 1], w[k + 2], V);
+                                if (pass && rej) st.add(kStCulledTiny);
+                                push(pass && !rej, d, tri[k], fill_id);
+                            }
+                        }
+                    };
+                    if (D.view & kDrawInterior) body(std::true_type{});
+                    else body(std::false_type{});
+                }
+                continue;
+            }
+            // not a strip everywhere: one triangle at a time over all draws (its index, validity
+            // and id picked by value, so the per-lane arrays stay in registers)
+#pragma unroll 1
+            for (int k = 0; k < TPT; ++k) {
+                uint32_t i3[3] = {vi[0][0], vi[0][1], vi[0][2]};
+                bool vk = valid[0];
+                uint32_t tk = tri[0];
+#pragma unroll
+                for (int j = 1; j < TPT; ++j) {
+                    const uint32_t a0 = vi[j][0], a1 = vi[j][1], a2 = vi[j][2], tj = tri[j];
+                    const bool vj = valid[j];
+                    i3[0] = k == j ? a0 : i3[0];
+                    i3[1] = k == j ? a1 : i3[1];
+                    i3[2] = k == j ? a2 : i3[2];
+                    vk = k == j ? vj : vk;
+                    tk = k == j ? tj : tk;
+                }
+                float p[9];
 #pragma unroll
                 for (int v = 0; v < 3; ++v) {
-                    in1[v] = (vi[k0][v] == vi[k1][0]) | (vi[k0][v] == vi[k1][1]) | (vi[k0][v] == vi[k1][2]);
-                    new1[v] = (vi[k1][v] != vi[k0][0]) & (vi[k1][v] != vi[k0][1]) & (vi[k1][v] != vi[k0][2]);
+                    const CURAST_GLOBAL float* src = gl(mesh.pos) + 3 * (size_t)(vk ? i3[v] : 0u);
+                    p[3 * v + 0] = src[0];
+                    p[3 * v + 1] = src[1];
+                    p[3 * v + 2] = src[2];
                 }
-                const int n_out = (int)!in1[0] + (int)!in1[1] + (int)!in1[2];
-                const int n_new = (int)new1[0] + (int)new1[1] + (int)new1[2];
-                const bool fits = valid[k0] && n_out == 1 && n_new == 1;
-                pair_ok[j] = __ballot(!valid[k1] || fits) == __ballot(1);
-                rotate_vertices(p[k0], !in1[0] ? 0 : !in1[1] ? 1 : 2);
-                rotate_vertices(p[k1], new1[0] ? 0 : new1[1] ? 1 : 2);
-            }
-        }
-        auto push = [&](bool need, uint32_t d, uint32_t t) {
-            const unsigned long long m = __ballot(need);
-            if (m) {
-                if (need) {
-                    IdEntry e;
-                    e.draw = d;
-                    e.tri = t;
-                    ring[(tail + rank_in(m)) & (kRing - 1)] = e;
-                }
-                tail += (uint32_t)__popcll(m);
-                if (tail - head >= 64) {
-                    wave_lds_sync();
-                    drain_ids<STATS>(a, d_views, d_meshes, d_draws, ring, head, 64, tiny_cull, early_out, st);
-                    head += 64;
-                    wave_lds_sync();
-                }
-            }
-        };
 #pragma unroll 1
-        for (uint32_t d = d0; d < d1; ++d) {
-            const DrawDesc& D = d_draws[d];
-            const ViewDesc V = d_views[D.view & kDrawViewMask];
-            auto body = [&](auto interior_tag) {
-                constexpr bool INTERIOR = decltype(interior_tag)::value;
-                auto win = [&](const float* q) -> float2 {
-                    if constexpr (INTERIOR) return fast_window_prescaled(D.R, D.A + 8, q[0], q[1], q[2]);
-                    else return fast_window(transform(D.A, q[0], q[1], q[2]), V);
-                };
-                auto reject = [&](float2 x, float2 y, float2 z) -> bool {
-                    if constexpr (INTERIOR) return fast_reject_box(x, y, z, V, tiny_cull);
-                    else return fast_reject(x, y, z, V, tiny_cull);
-                };
-                auto decide = [&](int k, bool rejected) {
-                    bool need = false;
-                    if (valid[k]) {
-                        st.add(kStTriDraws);
-                        need = !rejected;
-                        if (rejected) st.add(kStCulledTiny);
-                    }
-                    push(need, d, tri[k]);
-                };
-#pragma unroll
-                for (int j = 0; j < NP; ++j) {
-                    if (PAIRS && pair_ok[j]) {
-                        const int k0 = 2 * j, k1 = 2 * j + 1;
-                        const float2 w0 = win(p[k0] + 0), w1 = win(p[k0] + 3), w2 = win(p[k0] + 6);
-                        const float2 wn = win(p[k1] + 0);
-                        decide(k0, reject(w0, w1, w2));
-                        decide(k1, reject(w1, w2, wn));
-                    } else {
-#pragma unroll
-                        for (int k = PAIRS ? 2 * j : 0; k < (PAIRS ? 2 * j + 2 : TPT); ++k)
-                            decide(k, reject(win(p[k] + 0), win(p[k] + 3), win(p[k] + 6)));
-                    }
+                for (uint32_t d = d0; d < d1; ++d) {
+                    const DrawDesc& D = d_draws[d];
+                    const ViewDesc V = d_views[D.view & kDrawViewMask];
+                    auto body = [&](auto tag) {
+                        const bool rej = reject(tag, window(tag, D, V, p), window(tag, D, V, p + 3),
+                                                window(tag, D, V, p + 6), V);
+                        count(vk, rej);
+                        push(vk && !rej, d, tk, fill_id);
+                    };
+                    if (D.view & kDrawInterior) body(std::true_type{});
+                    else body(std::false_type{});
                 }
-            };
-            if (D.view & kDrawInterior) body(std::true_type{});
-            else body(std::false_type{});
+            }
+        } else {
+            float p[TPT][9];
+#pragma unroll
+            for (int k = 0; k < TPT; ++k)
+#pragma unroll
+                for (int v = 0; v < 3; ++v) {
+                    const CURAST_GLOBAL float* src = gl(mesh.pos) + 3 * (size_t)(valid[k] ? vi[k][v] : 0u);
+                    p[k][3 * v + 0] = src[0];
+                    p[k][3 * v + 1] = src[1];
+                    p[k][3 * v + 2] = src[2];
+                }
+#pragma unroll 1
+            for (uint32_t d = d0; d < d1; ++d) {
+                const DrawDesc& D = d_draws[d];
+                const ViewDesc V = d_views[D.view & kDrawViewMask];
+                auto body = [&](auto tag) {
+                    constexpr bool INTERIOR = decltype(tag)::value;
+#pragma unroll
+                    for (int k = 0; k < TPT; ++k) {
+                        // the exact clip coordinates go into the ring: general draws have them
+                        // from the window computation, interior ones compute them when pushing
+                        Clip c[3];
+                        float2 w[3];
+#pragma unroll
+                        for (int v = 0; v < 3; ++v) {
+                            if constexpr (INTERIOR) {
+                                w[v] = window(tag, D, V, p[k] + 3 * v);
+                            } else {
+                                c[v] = transform(D.A, p[k][3 * v], p[k][3 * v + 1], p[k][3 * v + 2]);
+                                w[v] = fast_window(c[v], V);
+                            }
+                        }
+                        const bool rej = reject(tag, w[0], w[1], w[2], V);
+                        count(valid[k], rej);
+                        push(valid[k] && !rej, d, tri[k], [&](ClipEntry& e) {
+#pragma unroll
+                            for (int v = 0; v < 3; ++v) {
+                                const Clip cv = INTERIOR ? transform(D.A, p[k][3 * v], p[k][3 * v + 1], p[k][3 * v + 2])
+                                                         : c[v];
+                                e.c[3 * v] = cv.x;
+                                e.c[3 * v + 1] = cv.y;
+                                e.c[3 * v + 2] = cv.w;
+                            }
+                        });
+                    }
+                };
+                if (D.view & kDrawInterior) body(std::true_type{});
+                else body(std::false_type{});
+            }
         }
     }
     if (tail != head) {
         wave_lds_sync();
-        drain_ids<STATS>(a, d_views, d_meshes, d_draws, ring, head, tail - head, tiny_cull, early_out, st);
+        drain_ring<STATS>(a, d_views, d_meshes, d_draws, ring, head, tail - head, tiny_cull, early_out, st);
     }
     st.flush(a.stats);
 }
@@ -771,15 +954,15 @@ __global__ void __launch_bounds__(64) stage1_share_kernel(RasterArgs a, CURAST_D
                 const unsigned long long m = __ballot(need);
                 if (m) {
                     if (need) {
-                        IdEntry e;
+                        IdEntry& e = s_ring[(tail + rank_in(m)) & (kRing - 1)];
                         e.draw = d;
                         e.tri = tri[k];
-                        s_ring[(tail + rank_in(m)) & (kRing - 1)] = e;
+                        e.mesh = wi.mesh;
                     }
                     tail += (uint32_t)__popcll(m);
                     if (tail - head >= 64) {
                         __syncthreads();
-                        drain_ids<STATS>(a, d_views, d_meshes, d_draws, s_ring, head, 64, tiny_cull, early_out, st);
+                        drain_ring<STATS>(a, d_views, d_meshes, d_draws, s_ring, head, 64, tiny_cull, early_out, st);
                         head += 64;
                         __syncthreads();
                     }
@@ -790,7 +973,7 @@ __global__ void __launch_bounds__(64) stage1_share_kernel(RasterArgs a, CURAST_D
     }
     if (tail != head) {
         __syncthreads();
-        drain_ids<STATS>(a, d_views, d_meshes, d_draws, s_ring, head, tail - head, tiny_cull, early_out, st);
+        drain_ring<STATS>(a, d_views, d_meshes, d_draws, s_ring, head, tail - head, tiny_cull, early_out, st);
     }
     st.flush(a.stats);
 }
@@ -1119,36 +1302,36 @@ hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool
     }
 }
 
-template <int BLOCK, int TPT, bool PAIRS>
+template <int BLOCK, int TPT, bool STRIPS>
 static hipError_t stage1_fast_dispatch(const RasterArgs& a, bool stats, uint32_t grid, hipStream_t s)
 {
-    if (stats) stage1_fast_kernel<BLOCK, TPT, PAIRS, true><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
-    else stage1_fast_kernel<BLOCK, TPT, PAIRS, false><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    if (stats) stage1_fast_kernel<BLOCK, TPT, STRIPS, true><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    else stage1_fast_kernel<BLOCK, TPT, STRIPS, false><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
     return hipGetLastError();
 }
 
 template <int BLOCK>
-static hipError_t stage1_fast_tpt(const RasterArgs& a, uint32_t tpt, bool pairs, bool stats, uint32_t grid,
+static hipError_t stage1_fast_tpt(const RasterArgs& a, uint32_t tpt, bool strips, bool stats, uint32_t grid,
                                   hipStream_t s)
 {
     switch (tpt) {
     case 1: return stage1_fast_dispatch<BLOCK, 1, false>(a, stats, grid, s);
-    case 2: return pairs ? stage1_fast_dispatch<BLOCK, 2, true>(a, stats, grid, s)
-                         : stage1_fast_dispatch<BLOCK, 2, false>(a, stats, grid, s);
-    case 4: return pairs ? stage1_fast_dispatch<BLOCK, 4, true>(a, stats, grid, s)
-                         : stage1_fast_dispatch<BLOCK, 4, false>(a, stats, grid, s);
+    case 2: return strips ? stage1_fast_dispatch<BLOCK, 2, true>(a, stats, grid, s)
+                          : stage1_fast_dispatch<BLOCK, 2, false>(a, stats, grid, s);
+    case 4: return strips ? stage1_fast_dispatch<BLOCK, 4, true>(a, stats, grid, s)
+                          : stage1_fast_dispatch<BLOCK, 4, false>(a, stats, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool pairs, bool stats, uint32_t grid,
+hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool strips, bool stats, uint32_t grid,
                               hipStream_t s)
 {
     switch (block) {
-    case 64: return stage1_fast_tpt<64>(a, tpt, pairs, stats, grid, s);
-    case 128: return stage1_fast_tpt<128>(a, tpt, pairs, stats, grid, s);
-    case 256: return stage1_fast_tpt<256>(a, tpt, pairs, stats, grid, s);
-    case 512: return stage1_fast_tpt<512>(a, tpt, pairs, stats, grid, s);
+    case 64: return stage1_fast_tpt<64>(a, tpt, strips, stats, grid, s);
+    case 128: return stage1_fast_tpt<128>(a, tpt, strips, stats, grid, s);
+    case 256: return stage1_fast_tpt<256>(a, tpt, strips, stats, grid, s);
+    case 512: return stage1_fast_tpt<512>(a, tpt, strips, stats, grid, s);
     default: return hipErrorInvalidValue;
     }
 }

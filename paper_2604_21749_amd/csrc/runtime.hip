@@ -24,7 +24,7 @@
 namespace curast {
 hipError_t launch_clear(const RasterArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s);
-hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool pairs, bool stats, uint32_t grid,
+hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool strips, bool stats, uint32_t grid,
                               hipStream_t s);
 hipError_t launch_stage1_share(const RasterArgs& a, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s);
 hipError_t launch_stage1_overflow(const RasterArgs& a, uint32_t grid, hipStream_t s);
@@ -141,9 +141,9 @@ curast_options resolve_defaults(const curast_options& u, int cus)
     curast_options o = u;
     if (!o.small_px) o.small_px = 128;
     if (!o.medium_px) o.medium_px = 4096;
-    if (!o.s1_block) o.s1_block = 256;
+    if (!o.s1_block) o.s1_block = 128;
     if (!o.s1_tris_per_thread) o.s1_tris_per_thread = 4;
-    if (!o.s1_multi_tris_per_thread) o.s1_multi_tris_per_thread = 2;
+    if (!o.s1_multi_tris_per_thread) o.s1_multi_tris_per_thread = 4;
     if (!o.s1_draws_per_item) o.s1_draws_per_item = 64;
     if (!o.s2_waves) o.s2_waves = (uint32_t)cus * 4;
     if (!o.s3_blocks) o.s3_blocks = (uint32_t)cus * 2;
@@ -599,8 +599,9 @@ int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, uint32_t grid_s
             a1.part = part;
             if (part == 1 && mode == 3) return launch_stage1_share(a1, tpt, stats, grid, s);
             if (mode == 1) return launch_stage1(a1, blk, tpt, stats, grid, s);
-            const bool pairs = part == 1 && !(ctx->opt.flags & kFlagNoPairs);
-            return launch_stage1_fast(a1, blk, tpt, pairs, stats, grid, s);
+            const bool strips =
+                !(ctx->opt.flags & kFlagNoStrips) && (part == 1 || (ctx->opt.flags & kFlagSingleStrips));
+            return launch_stage1_fast(a1, blk, tpt, strips, stats, grid, s);
         };
         if (grid_share) {
             e = launch_part(1, ctx->opt.s1_multi_tris_per_thread, grid_share);

@@ -90,6 +90,8 @@ OPTION_SWEEP = [
     dict(flags=api.FLAG_S3_PER_PART), dict(flags=api.FLAG_S3_PER_PART, medium_px=1),
     dict(medium_px=1, s3_blocks=3), dict(medium_px=64, q3_capacity=7),
     dict(s1_multi_tris_per_thread=4, s1_tris_per_thread=1), dict(s1_multi_tris_per_thread=1, s1_block=512),
+    dict(flags=api.FLAG_SINGLE_STRIPS), dict(flags=api.FLAG_SINGLE_STRIPS, s1_tris_per_thread=2, s1_block=64),
+    dict(flags=api.FLAG_SINGLE_STRIPS | api.FLAG_NO_TINY_CULL, small_px=1),
 ]
 
 
@@ -166,10 +168,10 @@ def test_stats_account_for_every_triangle(mode):
     assert st["q2_entries"] >= 2 and st["q3_entries"] > 0 and st["fragments"] > 0
 
 
-def _edge_pair_scene(seed):
-    """Instanced meshes whose consecutive triangles share edges (UV sphere, unshuffled height-field
-    patch), a copy with a few triangles moved out of order, degenerate duplicates and an odd
-    count, drawn near and far, inside the frustum and across its sides and near plane."""
+def _strip_scene(seed):
+    """Instanced meshes whose consecutive triangles form strips (UV sphere bands, unshuffled
+    height-field rows), a copy with a few triangles moved out of order, degenerate duplicates and
+    an odd count, drawn near and far, inside the frustum and across its sides and near plane."""
     rng = np.random.default_rng(seed)
     pos, idx = W.uv_sphere(24, 48, 1.0)
     hpos, hidx = W.heightfield(33, 0.15, 5 + seed, shuffle=False)
@@ -189,24 +191,26 @@ def _edge_pair_scene(seed):
               W.Mesh(hpos, hidx, inst=inst[::-1].copy(), bsphere=W.bounding_sphere(hpos)),
               W.Mesh(pos, broken, inst=inst[3:].copy(), bsphere=W.bounding_sphere(pos))]
     vp = W.camera((0.0, 0.0, 0.0), (0.0, 0.0, -1.0), aspect=256 / 192)
-    return W.Scene(f"pairs_{seed}", meshes, [W.View(vp, 0.05, 256, 192)])
+    return W.Scene(f"strips_{seed}", meshes, [W.View(vp, 0.05, 256, 192)])
 
 
 @pytest.mark.parametrize("opts", [
-    {}, dict(flags=api.FLAG_NO_PAIRS), dict(flags=api.FLAG_NO_FAST_INTERIOR),
-    dict(flags=api.FLAG_NO_PAIRS | api.FLAG_NO_FAST_INTERIOR), dict(s1_multi_tris_per_thread=4),
+    {}, dict(flags=api.FLAG_NO_STRIPS), dict(flags=api.FLAG_NO_FAST_INTERIOR),
+    dict(flags=api.FLAG_NO_STRIPS | api.FLAG_NO_FAST_INTERIOR), dict(s1_multi_tris_per_thread=4),
     dict(s1_multi_tris_per_thread=4, s1_block=64), dict(s1_multi_tris_per_thread=2, s1_block=512),
     dict(flags=api.FLAG_NO_TINY_CULL), dict(s1_mode=2, small_px=1, medium_px=1),
+    dict(flags=api.FLAG_SINGLE_STRIPS, s1_draws_per_item=3),
 ])
-def test_edge_sharing_pairs_and_interior_draws(opts):
-    """The pair path (four window positions per edge-sharing triangle pair) and the prescaled
-    interior rows reject only what the exact path would: bit-identical to the oracle."""
+def test_strips_and_interior_draws(opts):
+    """The strip path (shared window positions and one union-box test per strip of 2 or 4
+    triangles) and the prescaled interior rows reject only what the exact path would:
+    bit-identical to the oracle."""
     with api.Context(**opts) as c:
         for seed in range(3):
-            s = _edge_pair_scene(seed)
+            s = _strip_scene(seed)
             gm = gpu_meshes(s)
             visible, _, counts = api.plan(gm, s.views)
             if not (opts.get("flags", 0) & api.FLAG_NO_FAST_INTERIOR):
                 assert (visible == 2).sum() > 5, counts
             vis = c.rasterize_meshes(gm, s.views[0])
-            assert_vis_equal(api.as_uint64(vis), O.rasterize(s.meshes, s.views[0]), f"pairs seed {seed} {opts}")
+            assert_vis_equal(api.as_uint64(vis), O.rasterize(s.meshes, s.views[0]), f"strips seed {seed} {opts}")
