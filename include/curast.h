@@ -92,7 +92,7 @@ typedef struct {
     uint32_t medium_px;         /* stage-2 limit (default 4096, Sec. 4) */
     uint32_t s1_block;          /* stage-1 workgroup size: 64, 128, 256 or 512 (default 128, Sec. 4.1) */
     uint32_t s1_tris_per_thread;/* triangles per thread per stage-1 work item of a mesh drawn once:
-                                   1, 2 or 4 (default 4) */
+                                   1, 2, 4 or 8 (default 4) */
     uint32_t s1_draws_per_item; /* (instance x view) draws per stage-1 work item (default 64, Sec. 4.5) */
     uint32_t s2_waves;          /* persistent stage-2 wavefronts (default 4 per CU) */
     uint32_t s3_blocks;         /* persistent stage-3 workgroups (default 2 per CU) */

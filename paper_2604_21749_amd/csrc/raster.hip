@@ -1287,6 +1287,7 @@ static hipError_t stage1_tpt(const RasterArgs& a, uint32_t tpt, bool stats, uint
     case 1: return stage1_dispatch<BLOCK, 1>(a, stats, grid, s);
     case 2: return stage1_dispatch<BLOCK, 2>(a, stats, grid, s);
     case 4: return stage1_dispatch<BLOCK, 4>(a, stats, grid, s);
+    case 8: return stage1_dispatch<BLOCK, 8>(a, stats, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1320,6 +1321,7 @@ static hipError_t stage1_fast_tpt(const RasterArgs& a, uint32_t tpt, bool strips
                           : stage1_fast_dispatch<BLOCK, 2, false>(a, stats, grid, s);
     case 4: return strips ? stage1_fast_dispatch<BLOCK, 4, true>(a, stats, grid, s)
                           : stage1_fast_dispatch<BLOCK, 4, false>(a, stats, grid, s);
+    case 8: return strips ? hipErrorInvalidValue : stage1_fast_dispatch<BLOCK, 8, false>(a, stats, grid, s);
     default: return hipErrorInvalidValue;
     }
 }

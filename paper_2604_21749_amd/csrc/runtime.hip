@@ -123,8 +123,9 @@ int validate_options(const curast_options& o, std::string& msg)
     auto bad = [&](const char* m) { msg = m; return CURAST_E_INVALID; };
     if (o.s1_block && o.s1_block != 64 && o.s1_block != 128 && o.s1_block != 256 && o.s1_block != 512)
         return bad("s1_block must be 64, 128, 256 or 512");
-    if (o.s1_tris_per_thread && o.s1_tris_per_thread != 1 && o.s1_tris_per_thread != 2 && o.s1_tris_per_thread != 4)
-        return bad("s1_tris_per_thread must be 1, 2 or 4");
+    if (o.s1_tris_per_thread && o.s1_tris_per_thread != 1 && o.s1_tris_per_thread != 2 && o.s1_tris_per_thread != 4 &&
+        o.s1_tris_per_thread != 8)
+        return bad("s1_tris_per_thread must be 1, 2, 4 or 8");
     if (o.s1_multi_tris_per_thread && o.s1_multi_tris_per_thread != 1 && o.s1_multi_tris_per_thread != 2 &&
         o.s1_multi_tris_per_thread != 4)
         return bad("s1_multi_tris_per_thread must be 1, 2 or 4");
@@ -599,8 +600,8 @@ int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, uint32_t grid_s
             a1.part = part;
             if (part == 1 && mode == 3) return launch_stage1_share(a1, tpt, stats, grid, s);
             if (mode == 1) return launch_stage1(a1, blk, tpt, stats, grid, s);
-            const bool strips =
-                !(ctx->opt.flags & kFlagNoStrips) && (part == 1 || (ctx->opt.flags & kFlagSingleStrips));
+            const bool strips = !(ctx->opt.flags & kFlagNoStrips) && (tpt == 2 || tpt == 4) &&
+                                (part == 1 || (ctx->opt.flags & kFlagSingleStrips));
             return launch_stage1_fast(a1, blk, tpt, strips, stats, grid, s);
         };
         if (grid_share) {

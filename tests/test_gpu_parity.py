@@ -92,6 +92,8 @@ OPTION_SWEEP = [
     dict(s1_multi_tris_per_thread=4, s1_tris_per_thread=1), dict(s1_multi_tris_per_thread=1, s1_block=512),
     dict(flags=api.FLAG_SINGLE_STRIPS), dict(flags=api.FLAG_SINGLE_STRIPS, s1_tris_per_thread=2, s1_block=64),
     dict(flags=api.FLAG_SINGLE_STRIPS | api.FLAG_NO_TINY_CULL, small_px=1),
+    dict(s1_tris_per_thread=8), dict(s1_tris_per_thread=8, s1_block=512, s1_mode=1),
+    dict(s1_tris_per_thread=8, s1_block=64, flags=api.FLAG_SINGLE_STRIPS),
 ]
 
 
