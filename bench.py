@@ -104,8 +104,78 @@ def run_headline(args, api, torch, W):
     stage_ms["frame_gpu"] = sum(stage_ms.values())
     log(f"[bench] {args.steps} frames: {ms:.3f} ms/frame wall, stages {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})}")
     multi, single = split_meshes(api, scene, gm)
-    return {"scene": scene, "gm": gm, "ctx": ctx, "vis": vis, "ms": ms, "stage_ms": stage_ms,
+    ss = {} if args.no_secondary else run_supersampling(args, api, torch, ctx, gm, attrs, view, ms)
+    cmp = {} if args.no_secondary else run_compressed(args, api, torch, ctx, gm, attrs, view, vis_count)
+    return {"scene": scene, "gm": gm, "ctx": ctx, "vis": vis, "ms": ms, "stage_ms": stage_ms, "supersampling": ss,
+            "compressed": cmp,
             "visible": vis_count, "stats": st, "multi": multi, "single": single, "options": ctx.options()}
+
+
+def run_supersampling(args, api, torch, ctx, gm, attrs, view, ms_plain):
+    """The headline frame with 2x2 and 4x4 supersampling (Sec. 5, Table 5): rasterize at k times
+    the resolution, resolve every sample and average k x k blocks into the 3840x2160 image."""
+    from paper_2604_21749_amd.workloads import View
+    res = {"no_ss_ms": round(ms_plain, 3)}
+    out = torch.empty((view.height, view.width, 3), dtype=torch.float32, device="cuda")
+    for k in (2, 4):
+        hi = View(view.vp, view.near, view.width * k, view.height * k)
+        vis = torch.empty((hi.height, hi.width), dtype=torch.int64, device="cuda")
+
+        def frame():
+            ctx.rasterize_meshes(gm, hi, out=vis)
+            ctx.resolve(gm, hi, vis, attrs, out=out, samples_per_axis=k)
+        frame()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        reps = max(2, args.steps // 4)
+        for _ in range(reps):
+            frame()
+        torch.cuda.synchronize()
+        res[f"ss{k}x{k}_ms"] = round((time.perf_counter() - t1) * 1000.0 / reps, 3)
+        del vis
+        torch.cuda.empty_cache()
+    log(f"[bench] supersampling {res}")
+    return res
+
+
+def run_compressed(args, api, torch, ctx, gm, attrs, view, visible):
+    """The headline frame with every mesh compressed (Sec. 4.6: bit-packed indices, 16-bit
+    positions): geometry bytes, ms/frame and the single-draw stage-1 launch."""
+    t0 = time.perf_counter()
+    cm = [ctx.compress(g) for g in gm]
+    torch.cuda.synchronize()
+    compress_s = time.perf_counter() - t0
+    vis = torch.empty((view.height, view.width), dtype=torch.int64, device="cuda")
+    out = torch.empty((view.height, view.width, 3), dtype=torch.float32, device="cuda")
+
+    def frame():
+        ctx.rasterize_meshes(cm, view, out=vis)
+        ctx.resolve(cm, view, vis, attrs, out=out)
+    frame()
+    torch.cuda.synchronize()
+    ctx.reset_stage_times()
+    reps = max(2, args.steps // 2)
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        frame()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t1) * 1000.0 / reps
+    st = ctx.stage_times()
+    n = max(1, st["frames"])
+    plain_bytes = int(sum(g.pos.numel() * 4 + g.idx.numel() * 4 for g in gm))
+    comp_bytes = int(sum(c.compressed.packed.numel() * 4 + c.compressed.qpos.numel() * 2 for c in cm))
+    single = [c for c, g in zip(cm, gm) if g.num_instances == 1]
+    single_bytes = int(sum(c.compressed.packed.numel() * 4 + c.compressed.qpos.numel() * 2 for c in single))
+    res = {"geometry_bytes_plain": plain_bytes, "geometry_bytes_compressed": comp_bytes,
+           "index_bits": [c.compressed.index_bits for c in cm], "compress_s": round(compress_s, 3),
+           "ms_per_frame": round(ms, 3), "gtris_s": round(visible / (ms * 1e-3) / 1e9, 2),
+           "stage1_single_ms": round(st["stage1_single"] / n, 4), "stage1_multi_ms": round(st["stage1_multi"] / n, 4),
+           "stage1_single_hbm_frac": round(single_bytes / max(st["stage1_single"] / n * 1e-3, 1e-12) / 1e9
+                                           / HBM_PEAK_GBS, 4)}
+    log(f"[bench] compressed {res}")
+    del cm, vis, out
+    torch.cuda.empty_cache()
+    return res
 
 
 def read_traffic(kernel: str):
@@ -138,8 +208,8 @@ def stage1_rooflines(h):
     sm = h["stage_ms"]
     o = h["options"]
     strips = "true" if (o["s1_multi_tris_per_thread"] in (2, 4) and not (o["flags"] & 0x100)) else "false"
-    k_single = f"stage1_fast_kernel<{o['s1_block']}, {o['s1_tris_per_thread']}, false, false>"
-    k_multi = f"stage1_fast_kernel<{o['s1_block']}, {o['s1_multi_tris_per_thread']}, {strips}, false>"
+    k_single = f"stage1_fast_kernel<{o['s1_block']}, {o['s1_tris_per_thread']}, false, false, 0>"
+    k_multi = f"stage1_fast_kernel<{o['s1_block']}, {o['s1_multi_tris_per_thread']}, {strips}, false, 0>"
     single_bytes = stage1_algorithmic_bytes(h["single"])
     single_ach = single_bytes / max(sm["stage1_single"] * 1e-3, 1e-12) / 1e9
     tri_inst = int(sum(m.num_triangles * m.num_instances for m in h["multi"]))
@@ -326,6 +396,8 @@ def main():
         "roofline": rl_main,
         "roofline_other_stage1_launch": rl_other,
         "gtris_s_submitted": round(scene.total_tri_instances / (h["ms"] * 1e-3) / 1e9, 4),
+        "supersampling": h["supersampling"],
+        "compressed": h["compressed"],
     }
     st = h["stats"]
     result["stage_counts"] = {k: st[k] for k in ("culled_near", "culled_frustum", "culled_tiny", "culled_backface",

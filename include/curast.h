@@ -111,6 +111,26 @@ typedef struct {
                                    (default 4) */
 } curast_options;
 
+/*
+ * Compressed mesh geometry (Sec. 4.6, "Compression"): indices bit-packed relative to the mesh's
+ * smallest index, positions as 16-bit fixed point relative to the mesh's bounding box.  A
+ * compressed mesh renders exactly as the uncompressed mesh made of its decoded indices and
+ * positions:
+ *   index i (0 <= i < 3T)  = index_min + bits [i * index_bits, (i + 1) * index_bits) of the
+ *                            little-endian bit stream `indices` (uint32 words, bit 0 first);
+ *   position component c   = fmaf((float)positions[3 v + c], step[c], lo[c]).
+ * curast_compress_prepare computes index_min, index_bits, lo and step; curast_compress fills the
+ * two buffers.  The buffers are the caller's (device memory).
+ */
+typedef struct {
+    const uint32_t* indices;    /* device, curast_compress_prepare's index_words uint32 words */
+    const uint16_t* positions;  /* device [V][3] quantized positions */
+    uint32_t index_min;         /* smallest index of the mesh */
+    uint32_t index_bits;        /* ceil(log2(max - min + 1)), at least 1 and at most 32 */
+    float lo[3];                /* bounding-box minimum */
+    float step[3];              /* (float)(((double)max - (double)min) / 65535) per axis */
+} curast_compressed;
+
 typedef struct {
     const float* vertices;      /* device [V][3] object-space positions */
     uint32_t num_vertices;      /* V */
@@ -121,6 +141,8 @@ typedef struct {
     uint32_t num_instances;     /* N (ignored when instances is NULL) */
     float bsphere[4];           /* object-space bounding sphere (cx, cy, cz, r) containing every
                                    vertex, used for the host frustum cull; r <= 0: unknown */
+    const curast_compressed* compressed; /* host, or NULL; when set, the mesh's geometry is read
+                                   from it and `vertices` / `indices` are not used */
 } curast_mesh;
 
 typedef struct {
@@ -200,6 +222,25 @@ int curast_project(curast_ctx* ctx, const curast_mesh* mesh, uint32_t instance,
                    const curast_view* view, float* pos_ss, void* stream);
 
 /*
+ * Compression (Sec. 4.6), step 1: from the uncompressed mesh (vertices and indices set), the
+ * smallest and largest index and the positions' bounding box, giving info->index_min,
+ * index_bits, lo and step, and the size of the packed index stream in uint32 words
+ * (ceil(3 T index_bits / 32) + 1).  Synchronizes the stream.  info->indices / positions are not
+ * touched.
+ */
+int curast_compress_prepare(curast_ctx* ctx, const curast_mesh* mesh, curast_compressed* info,
+                            uint64_t* index_words, void* stream);
+
+/*
+ * Compression, step 2: writes the packed indices (index_words words, every bit defined) and the
+ * quantized positions q = clamp(rint((p - lo) * scale), 0, 65535) with
+ * scale = (float)(1.0 / (double)step) per axis (0 for a flat axis), the subtraction and product
+ * in binary32, rint rounding half to even.
+ */
+int curast_compress(curast_ctx* ctx, const curast_mesh* mesh, const curast_compressed* info,
+                    uint32_t* packed_indices, uint16_t* positions, void* stream);
+
+/*
  * Resolve a view's visibility buffer into interpolated attributes (Sec. 4.4): per pixel decode
  * the 36-bit ID, binary-search the (mesh, instance) in the int64 prefix of triangle counts,
  * recompute the three vertices and interpolate perspective-correctly at the pixel centre.
@@ -208,6 +249,21 @@ int curast_project(curast_ctx* ctx, const curast_mesh* mesh, uint32_t instance,
  */
 int curast_resolve(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* view,
                    const float* const* attrs, uint32_t C, float* out, void* stream);
+
+/*
+ * Supersampled resolve (anti-aliasing, Sec. 5 "Anti-Aliasing (Super Sampling)", Table 5):
+ * `view` is the view at samples_per_axis times the output size in each direction (same
+ * view_proj), whose visibility buffer curast_rasterize_meshes filled, so every output pixel owns
+ * a samples_per_axis x samples_per_axis block of samples at regular offsets.  Each sample is
+ * resolved as in curast_resolve; the output pixel is their fp32 sum, taken row by row with empty
+ * samples adding 0, times 1 / samples_per_axis^2.
+ *   samples_per_axis: 1, 2 or 4 (1 is curast_resolve); the view's width and height must be
+ *   multiples of it;
+ *   out: device [height / s][width / s][C] float.  1 <= C <= 16.
+ */
+int curast_resolve_supersampled(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* view,
+                                uint32_t samples_per_axis, const float* const* attrs, uint32_t C, float* out,
+                                void* stream);
 
 /*
  * Resolve one mesh from explicit screen positions (the differentiable form):

@@ -45,6 +45,8 @@ def lib():
             "orc_coverage_counts": [P, C.c_uint32, P, P, P],
             "orc_rasterize_brute": [P, C.c_uint32, P, P],
             "orc_project": [P, C.c_uint32, P, P],
+            "orc_quantize_positions": [P, C.c_uint32, P, P, P],
+            "orc_decode_positions": [P, C.c_uint32, P, P, P],
             "orc_resolve": [P, C.c_uint32, P, P, P, C.c_uint32, P, C.c_int],
             "orc_resolve_screen": [P, C.c_int32, C.c_int32, P, C.c_uint64, C.c_int64, P, C.c_uint32, P, C.c_uint32, P],
             "orc_resolve_screen_f64": [P, C.c_int32, C.c_int32, P, C.c_uint64, C.c_int64, P, C.c_uint32, P, C.c_uint32, P],
@@ -167,6 +169,97 @@ def resolve(meshes, view, vis: np.ndarray, attrs: Sequence[np.ndarray], threads:
     _check(lib().orc_resolve(pk.meshes, pk.M, C.byref(pk.view), vis.ctypes.data, ptrs, C_, out.ctypes.data,
                              threads), "resolve")
     return out
+
+
+# ----------------------------------------------------------------------------------------------
+# compressed geometry (Sec. 4.6)
+# ----------------------------------------------------------------------------------------------
+def index_bits(span: int) -> int:
+    """Bits per packed index for indices spanning [min, min + span]: the paper's ceil(log2(span))
+    read as ceil(log2(span + 1)), the width that holds span itself; at least 1."""
+    return max(1, int(span).bit_length())
+
+
+def compress_indices(idx: np.ndarray):
+    """(index_min, bits, packed uint32 words): index i of the flattened [T, 3] array minus
+    index_min occupies bits [i bits, (i + 1) bits) of a little-endian stream, plus one word of
+    padding.  Written bit by bit (small meshes only)."""
+    flat = np.ascontiguousarray(idx, np.uint32).reshape(-1).astype(np.uint64)
+    lo = int(flat.min()) if flat.size else 0
+    hi = int(flat.max()) if flat.size else 0
+    b = index_bits(hi - lo)
+    words = np.zeros((flat.size * b + 31) // 32 + 1, np.uint64)
+    vals = flat - np.uint64(lo)
+    for j in range(b):
+        bit = (vals >> np.uint64(j)) & np.uint64(1)
+        pos = np.arange(flat.size, dtype=np.uint64) * np.uint64(b) + np.uint64(j)
+        np.bitwise_or.at(words, (pos >> np.uint64(5)).astype(np.int64), bit << (pos & np.uint64(31)))
+    return lo, b, words.astype(np.uint32)
+
+
+def decompress_indices(words: np.ndarray, index_min: int, bits: int, T: int) -> np.ndarray:
+    w = np.asarray(words, np.uint32).astype(np.uint64)
+    out = np.zeros(3 * T, np.uint64)
+    for j in range(bits):
+        pos = np.arange(3 * T, dtype=np.uint64) * np.uint64(bits) + np.uint64(j)
+        out |= ((w[(pos >> np.uint64(5)).astype(np.int64)] >> (pos & np.uint64(31))) & np.uint64(1)) << np.uint64(j)
+    return (out + np.uint64(index_min)).astype(np.uint32).reshape(T, 3)
+
+
+def position_box(pos: np.ndarray):
+    """(lo, step) per axis: lo = the minimum, step = (float)(((double)max - (double)min) / 65535)."""
+    p = np.asarray(pos, np.float32)
+    lo = p.min(axis=0) if p.size else np.zeros(3, np.float32)
+    hi = p.max(axis=0) if p.size else np.zeros(3, np.float32)
+    step = ((hi.astype(np.float64) - lo.astype(np.float64)) / 65535.0).astype(np.float32)
+    return lo.astype(np.float32), step
+
+
+def quantize_positions(pos: np.ndarray, lo, step) -> np.ndarray:
+    p = np.ascontiguousarray(pos, np.float32)
+    out = np.empty(p.shape, np.uint16)
+    lo = np.ascontiguousarray(lo, np.float32)
+    step = np.ascontiguousarray(step, np.float32)
+    _check(lib().orc_quantize_positions(p.ctypes.data, p.shape[0], lo.ctypes.data, step.ctypes.data,
+                                        out.ctypes.data), "quantize")
+    return out
+
+
+def decode_positions(q: np.ndarray, lo, step) -> np.ndarray:
+    q = np.ascontiguousarray(q, np.uint16)
+    out = np.empty(q.shape, np.float32)
+    lo = np.ascontiguousarray(lo, np.float32)
+    step = np.ascontiguousarray(step, np.float32)
+    _check(lib().orc_decode_positions(q.ctypes.data, q.shape[0], lo.ctypes.data, step.ctypes.data,
+                                      out.ctypes.data), "decode")
+    return out
+
+
+def decompressed_mesh(m, words, index_min, bits, qpos, lo, step):
+    """The uncompressed mesh a compressed one renders as (same instances, bounding sphere)."""
+    from dataclasses import replace
+    return replace(m, pos=decode_positions(qpos, lo, step),
+                   idx=decompress_indices(words, index_min, bits, m.idx.shape[0]))
+
+
+def box_filter(samples: np.ndarray, k: int) -> np.ndarray:
+    """Mean of each k x k block of resolved samples [k H, k W, C] -> [H, W, C] (the supersampled
+    resolve, Sec. 5 "Anti-Aliasing (Super Sampling)"): an fp32 sum over the block's rows, then its
+    columns, in that order, times 1 / k^2 (exact)."""
+    kH, kW, C_ = samples.shape
+    if kH % k or kW % k:
+        raise ValueError("sample grid not a multiple of k")
+    samples = np.asarray(samples, np.float32)
+    acc = np.zeros((kH // k, kW // k, C_), np.float32)
+    for sy in range(k):
+        for sx in range(k):
+            acc += samples[sy::k, sx::k]
+    return acc * np.float32(1.0 / (k * k))
+
+
+def resolve_supersampled(meshes, view_hi, vis_hi: np.ndarray, attrs, k: int, threads: int = 0) -> np.ndarray:
+    """Resolve every sample of the k-times-larger view, then box-filter k x k blocks."""
+    return box_filter(resolve(meshes, view_hi, vis_hi, attrs, threads=threads), k)
 
 
 def resolve_screen(vis, idx, id_base, pos_ss, attrs) -> np.ndarray:

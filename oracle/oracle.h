@@ -99,6 +99,11 @@ int orc_coverage_counts(const orc_mesh* meshes, uint32_t M, const orc_view* view
 int orc_rasterize_brute(const orc_mesh* meshes, uint32_t M, const orc_view* view, uint64_t* vis);
 
 /* Unsnapped screen positions (sx, sy, w) of every vertex of one mesh instance: [V][3]. */
+/* Compressed geometry (Sec. 4.6): binary32 quantization of positions to 16 bits relative to lo with
+ * scale (float)(1 / (double)step) (0 for step 0), and the decoding fmaf(q, step, lo). */
+int orc_quantize_positions(const float* pos, uint32_t V, const float lo[3], const float step[3], uint16_t* out);
+int orc_decode_positions(const uint16_t* q, uint32_t V, const float lo[3], const float step[3], float* out);
+
 int orc_project(const orc_mesh* mesh, uint32_t instance, const orc_view* view, float* pos_ss);
 
 /* fp32 resolve of a visibility buffer: out [H][W][C]; attrs[m] is mesh m's [V][C]. */

@@ -49,10 +49,15 @@ class Options(C.Structure):
         "s1_multi_tris_per_thread")]
 
 
+class CompressedStruct(C.Structure):
+    _fields_ = [("indices", C.c_void_p), ("positions", C.c_void_p), ("index_min", C.c_uint32),
+                ("index_bits", C.c_uint32), ("lo", C.c_float * 3), ("step", C.c_float * 3)]
+
+
 class MeshStruct(C.Structure):
     _fields_ = [("vertices", C.c_void_p), ("num_vertices", C.c_uint32), ("indices", C.c_void_p),
                 ("num_triangles", C.c_uint64), ("instances", C.c_void_p), ("num_instances", C.c_uint32),
-                ("bsphere", C.c_float * 4)]
+                ("bsphere", C.c_float * 4), ("compressed", C.c_void_p)]
 
 
 class ViewStruct(C.Structure):
@@ -80,6 +85,9 @@ SIGNATURES = {
     "curast_rasterize_batched": (C.c_int, [_P, _P, C.c_uint32, _P, C.c_uint32, _P]),
     "curast_project": (C.c_int, [_P, _P, C.c_uint32, _P, _P, _P]),
     "curast_resolve": (C.c_int, [_P, _P, C.c_uint32, _P, _P, C.c_uint32, _P, _P]),
+    "curast_compress_prepare": (C.c_int, [_P, _P, _P, _P, _P]),
+    "curast_compress": (C.c_int, [_P, _P, _P, _P, _P, _P]),
+    "curast_resolve_supersampled": (C.c_int, [_P, _P, C.c_uint32, _P, C.c_uint32, _P, C.c_uint32, _P, _P]),
     "curast_resolve_screen": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, C.c_uint64, C.c_uint64, _P, C.c_uint32,
                                         _P, C.c_uint32, _P, _P]),
     "curast_resolve_backward": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, C.c_uint64, C.c_uint64, _P,
@@ -140,16 +148,30 @@ def _check_cuda(t: torch.Tensor, dtype, name: str, shape_last=None):
 
 @dataclass
 class GpuMesh:
-    """A mesh whose vertices and indices live in device memory (indices as int32 bits of uint32)."""
-    pos: torch.Tensor                       # float32 [V, 3] (cuda)
-    idx: torch.Tensor                       # int32 [T, 3] (cuda)
+    """A mesh whose vertices and indices live in device memory (indices as int32 bits of uint32),
+    or whose geometry is compressed (pos and idx None, `compressed` set)."""
+    pos: Optional[torch.Tensor]             # float32 [V, 3] (cuda)
+    idx: Optional[torch.Tensor]             # int32 [T, 3] (cuda)
     inst: Optional[np.ndarray] = None       # float32 [N, 12] host, or None
     bsphere: Optional[np.ndarray] = None    # float32 [4] host, or None
     attrs: Optional[torch.Tensor] = None    # float32 [V, C] (cuda), for resolve
+    compressed: Optional["CompressedGeometry"] = None
 
     @property
     def num_instances(self) -> int:
         return 1 if self.inst is None else int(self.inst.shape[0])
+
+    @property
+    def num_vertices(self) -> int:
+        return self.compressed.num_vertices if self.compressed is not None else int(self.pos.shape[0])
+
+    @property
+    def num_triangles(self) -> int:
+        return self.compressed.num_triangles if self.compressed is not None else int(self.idx.shape[0])
+
+    @property
+    def device(self):
+        return self.compressed.qpos.device if self.compressed is not None else self.pos.device
 
     @staticmethod
     def from_host(m, device="cuda") -> "GpuMesh":
@@ -162,15 +184,52 @@ class GpuMesh:
         return GpuMesh(pos, idx, inst, bs, attrs)
 
 
+@dataclass
+class CompressedGeometry:
+    """Device buffers and parameters of a compressed mesh (curast_compressed, Sec. 4.6)."""
+    packed: torch.Tensor                    # int32 [words] bits of the packed index stream (cuda)
+    qpos: torch.Tensor                      # int16 [V, 3] bits of the uint16 positions (cuda)
+    index_min: int
+    index_bits: int
+    lo: np.ndarray                          # float32 [3]
+    step: np.ndarray                        # float32 [3]
+    num_vertices: int
+    num_triangles: int
+
+    def struct(self) -> CompressedStruct:
+        c = CompressedStruct()
+        c.indices = self.packed.data_ptr() if self.packed.numel() else None
+        c.positions = self.qpos.data_ptr() if self.qpos.numel() else None
+        c.index_min = self.index_min
+        c.index_bits = self.index_bits
+        for k in range(3):
+            c.lo[k] = float(self.lo[k])
+            c.step[k] = float(self.step[k])
+        return c
+
+
 def _mesh_struct(m: GpuMesh, keep: list, check: bool = True) -> MeshStruct:
-    if check:
-        _check_cuda(m.pos, torch.float32, "vertices", 3)
-        _check_cuda(m.idx, torch.int32, "indices", 3)
     s = MeshStruct()
-    s.vertices = m.pos.data_ptr() if m.pos.numel() else None
-    s.num_vertices = m.pos.shape[0]
-    s.indices = m.idx.data_ptr() if m.idx.numel() else None
-    s.num_triangles = m.idx.shape[0]
+    if m.compressed is not None:
+        if check:
+            _check_cuda(m.compressed.packed, torch.int32, "packed indices")
+            _check_cuda(m.compressed.qpos, torch.int16, "quantized positions", 3)
+        cs = m.compressed.struct()
+        keep.append(cs)
+        s.compressed = C.addressof(cs)
+        s.vertices = None
+        s.indices = None
+        s.num_vertices = m.compressed.num_vertices
+        s.num_triangles = m.compressed.num_triangles
+    else:
+        if check:
+            _check_cuda(m.pos, torch.float32, "vertices", 3)
+            _check_cuda(m.idx, torch.int32, "indices", 3)
+        s.compressed = None
+        s.vertices = m.pos.data_ptr() if m.pos.numel() else None
+        s.num_vertices = m.pos.shape[0]
+        s.indices = m.idx.data_ptr() if m.idx.numel() else None
+        s.num_triangles = m.idx.shape[0]
     if m.inst is not None:
         inst = np.ascontiguousarray(m.inst, np.float32).reshape(-1, 12)
         keep.append(inst)
@@ -277,7 +336,7 @@ class Context:
         """curast_rasterize_meshes: a mesh list into one view (view: workloads.View-like)."""
         keep = []
         arr = (MeshStruct * max(1, len(meshes)))(*[_mesh_struct(m, keep) for m in meshes])
-        dev = meshes[0].pos.device if meshes else torch.device("cuda")
+        dev = meshes[0].device if meshes else torch.device("cuda")
         if out is None:
             out = torch.empty((view.height, view.width), dtype=torch.int64, device=dev)
         vs = _view_struct(view.vp, view.near, view.width, view.height, out)
@@ -288,7 +347,7 @@ class Context:
         """curast_rasterize_batched: the same meshes into many views in one graph launch."""
         keep = []
         arr = (MeshStruct * max(1, len(meshes)))(*[_mesh_struct(m, keep) for m in meshes])
-        dev = meshes[0].pos.device if meshes else torch.device("cuda")
+        dev = meshes[0].device if meshes else torch.device("cuda")
         if outs is None:
             outs = [torch.empty((v.height, v.width), dtype=torch.int64, device=dev) for v in views]
         vs = (ViewStruct * len(views))(*[_view_struct(v.vp, v.near, v.width, v.height, o) for v, o in zip(views, outs)])
@@ -300,33 +359,64 @@ class Context:
         keep = []
         ms = _mesh_struct(mesh, keep)
         if out is None:
-            out = torch.empty((mesh.pos.shape[0], 3), dtype=torch.float32, device=mesh.pos.device)
+            out = torch.empty((mesh.num_vertices, 3), dtype=torch.float32, device=mesh.device)
         _check_cuda(out, torch.float32, "pos_ss", 3)
         vs = _view_struct(view.vp, view.near, view.width, view.height, None)
         self._check(lib().curast_project(self._h, C.byref(ms), int(instance), C.byref(vs), out.data_ptr(),
-                                         _stream(mesh.pos.device)))
+                                         _stream(mesh.device)))
         return out
 
-    def resolve(self, meshes: Sequence[GpuMesh], view, vis: torch.Tensor, attrs: Sequence[torch.Tensor],
-                out: Optional[torch.Tensor] = None):
-        """curast_resolve: interpolated attributes float32 [H, W, C] of a visibility buffer."""
+    def compress(self, mesh: GpuMesh) -> GpuMesh:
+        """curast_compress_prepare + curast_compress: the same mesh with compressed geometry
+        (bit-packed indices, 16-bit positions; Sec. 4.6).  Instances, bounding sphere and
+        attributes are kept."""
         keep = []
+        ms = _mesh_struct(mesh, keep)
+        info = CompressedStruct()
+        words = C.c_uint64()
+        stream = _stream(mesh.device)
+        self._check(lib().curast_compress_prepare(self._h, C.byref(ms), C.byref(info), C.byref(words), stream))
+        packed = torch.empty(int(words.value), dtype=torch.int32, device=mesh.device)
+        qpos = torch.empty((mesh.num_vertices, 3), dtype=torch.int16, device=mesh.device)
+        self._check(lib().curast_compress(self._h, C.byref(ms), C.byref(info),
+                                          packed.data_ptr() if packed.numel() else None,
+                                          qpos.data_ptr() if qpos.numel() else None, stream))
+        geo = CompressedGeometry(packed, qpos, int(info.index_min), int(info.index_bits),
+                                 np.array(info.lo[:], np.float32), np.array(info.step[:], np.float32),
+                                 mesh.num_vertices, mesh.num_triangles)
+        return GpuMesh(None, None, mesh.inst, mesh.bsphere, mesh.attrs, geo)
+
+    def resolve(self, meshes: Sequence[GpuMesh], view, vis: torch.Tensor, attrs: Sequence[torch.Tensor],
+                out: Optional[torch.Tensor] = None, samples_per_axis: int = 1):
+        """curast_resolve: interpolated attributes float32 [H, W, C] of a visibility buffer.  With
+        samples_per_axis = s > 1 (curast_resolve_supersampled) `view` and `vis` are at s times the
+        output size and the result is [H / s, W / s, C], the mean of each pixel's s x s samples."""
+        keep = []
+        ss = int(samples_per_axis)
         arr = (MeshStruct * max(1, len(meshes)))(*[_mesh_struct(m, keep) for m in meshes])
         Cn = int(attrs[0].shape[1])
         for a in attrs:
             _check_cuda(a, torch.float32, "attrs", Cn)
         ptrs = (C.c_void_p * max(1, len(attrs)))(*[a.data_ptr() for a in attrs])
+        if ss < 1 or view.width % ss or view.height % ss:
+            raise ValueError("view size must be a multiple of samples_per_axis")
+        shape = (view.height // ss, view.width // ss, Cn)
         if out is None:
-            out = torch.empty((view.height, view.width, Cn), dtype=torch.float32, device=vis.device)
+            out = torch.empty(shape, dtype=torch.float32, device=vis.device)
         _check_cuda(out, torch.float32, "out")
-        if tuple(out.shape) != (view.height, view.width, Cn):
-            raise ValueError("out must have shape [H, W, C]")
+        if tuple(out.shape) != shape:
+            raise ValueError(f"out must have shape {list(shape)}")
         for m, a in zip(meshes, attrs):
-            if a.shape[0] != m.pos.shape[0]:
+            if a.shape[0] != m.num_vertices:
                 raise ValueError("attrs[m] must have one row per vertex of mesh m")
         vs = _view_struct(view.vp, view.near, view.width, view.height, vis)
-        self._check(lib().curast_resolve(self._h, arr, len(meshes), C.byref(vs), ptrs, Cn, out.data_ptr(),
-                                         _stream(vis.device)))
+        if ss == 1:
+            rc = lib().curast_resolve(self._h, arr, len(meshes), C.byref(vs), ptrs, Cn, out.data_ptr(),
+                                      _stream(vis.device))
+        else:
+            rc = lib().curast_resolve_supersampled(self._h, arr, len(meshes), C.byref(vs), ss, ptrs, Cn,
+                                                   out.data_ptr(), _stream(vis.device))
+        self._check(rc)
         return out
 
     def resolve_screen(self, vis: torch.Tensor, indices: torch.Tensor, pos_ss: torch.Tensor, attrs: torch.Tensor,

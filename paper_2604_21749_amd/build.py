@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["raster.hip", "resolve.hip", "runtime.hip", "autotune.hip"]
+SOURCES = ["raster.hip", "resolve.hip", "runtime.hip", "autotune.hip", "compress.hip"]
 LIB = os.path.join(HERE, "libcurast.so")
 ARCH = os.environ.get("CURAST_OFFLOAD_ARCH", "gfx950")
 

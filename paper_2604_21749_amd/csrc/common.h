@@ -44,11 +44,15 @@ struct ViewDesc {                 // 48 B
     uint32_t pad[2];
 };
 
-struct MeshDesc {                 // 32 B
-    const float* pos;             // [V][3]
-    const uint32_t* idx;          // [T][3]
+struct MeshDesc {                 // 80 B
+    const float* pos;             // [V][3], or NULL when compressed
+    const uint32_t* idx;          // [T][3], or the packed index stream when compressed
+    const uint16_t* qpos;         // [V][3] quantized positions when compressed, else NULL
     uint64_t T;
     uint32_t V;
+    uint32_t idx_bits;            // 0: plain indices; else bits per packed index
+    uint32_t idx_min;             // added to every packed index
+    float lo[3], step[3];         // position = fmaf(q, step, lo) when compressed
     uint32_t pad;
 };
 
@@ -140,6 +144,7 @@ struct RasterArgs {
     uint32_t* tile_count;         // [n_tiles] parts per tile (zeroed by the clear kernel)
     uint32_t* tile_offset;        // [n_tiles + 1] exclusive prefix of tile_count
     uint32_t* q3_binned;          // [q3_cap] large-record index of every part, grouped by tile
+    uint32_t compressed_parts;    // bit p: stage-1 part p has a compressed mesh (host-side choice)
 };
 
 struct ResolveArgs {
@@ -152,7 +157,8 @@ struct ResolveArgs {
     const float* const* attrs;    // [M] per-mesh attribute pointers
     uint32_t n_pairs;
     uint32_t C;
-    float* out;                   // [H][W][C]
+    float* out;                   // [H][W][C], or [H/ss][W/ss][C] when supersampled
+    uint32_t ss;                  // samples per axis and output pixel (1: no supersampling)
 };
 
 struct ScreenArgs {

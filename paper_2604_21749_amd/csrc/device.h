@@ -33,6 +33,54 @@ struct Clip {                 // clip-space vertex: x, y and the positive view d
     float x, y, w;
 };
 
+// ----------------------------------------------------------------------------------------------
+// Mesh geometry access, plain or compressed (Sec. 4.6).  Packed index i occupies bits
+// [i b, (i + 1) b) of a little-endian stream of 32-bit words; it is read with one 64-bit load of
+// the two words around it (the stream carries one word of padding).  A quantized position
+// component decodes as fmaf(q, step, lo).
+// ----------------------------------------------------------------------------------------------
+__device__ __forceinline__ uint32_t packed_index(const MeshDesc& M, uint64_t i)
+{
+    const uint64_t bit = i * (uint64_t)M.idx_bits;
+    const CURAST_GLOBAL uint32_t* w = gl(M.idx) + (bit >> 5);
+    const uint64_t pair = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+    const uint32_t mask = M.idx_bits >= 32 ? 0xFFFFFFFFu : ((1u << M.idx_bits) - 1u);
+    return M.idx_min + ((uint32_t)(pair >> (bit & 31)) & mask);
+}
+
+// Vertex indices of triangle t (CMP: the mesh is known to be compressed; otherwise decided per
+// mesh, which is uniform across the wavefront).
+template <int CMP = -1>
+__device__ __forceinline__ void mesh_triangle(const MeshDesc& M, uint64_t t, uint32_t (&v)[3])
+{
+    const bool packed = CMP < 0 ? M.idx_bits != 0 : CMP != 0;
+    if (packed) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[k] = packed_index(M, 3 * t + k);
+    } else {
+        const CURAST_GLOBAL uint32_t* ip = gl(M.idx) + 3 * t;
+        v[0] = ip[0];
+        v[1] = ip[1];
+        v[2] = ip[2];
+    }
+}
+
+template <int CMP = -1>
+__device__ __forceinline__ void mesh_vertex(const MeshDesc& M, uint32_t v, float (&p)[3])
+{
+    const bool packed = CMP < 0 ? M.qpos != nullptr : CMP != 0;
+    if (packed) {
+        const CURAST_GLOBAL uint16_t* q = gl(M.qpos) + 3 * (size_t)v;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) p[c] = __builtin_fmaf((float)q[c], M.step[c], M.lo[c]);
+    } else {
+        const CURAST_GLOBAL float* q = gl(M.pos) + 3 * (size_t)v;
+        p[0] = q[0];
+        p[1] = q[1];
+        p[2] = q[2];
+    }
+}
+
 // Row r of a draw matrix applied to an object-space point: fmaf(A0, vx, fmaf(A1, vy, fmaf(A2, vz, A3))).
 __device__ __forceinline__ float row_dot(const float* A, float vx, float vy, float vz)
 {

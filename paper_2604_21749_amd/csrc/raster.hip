@@ -301,16 +301,18 @@ __global__ void __launch_bounds__(BLOCK) stage1_kernel(RasterArgs a, CURAST_DESC
             bool valid = t < mesh.T;
             float p[9];
             if (valid) {
-                const CURAST_GLOBAL uint32_t* ip = gl(mesh.idx) + 3 * t;
-                const uint32_t i0 = ip[0], i1 = ip[1], i2 = ip[2];
-                valid = i0 < mesh.V && i1 < mesh.V && i2 < mesh.V;
+                uint32_t iv[3];
+                mesh_triangle(mesh, t, iv);
+                valid = iv[0] < mesh.V && iv[1] < mesh.V && iv[2] < mesh.V;
                 if (valid) {
-                    const CURAST_GLOBAL float* q0 = gl(mesh.pos) + 3 * (size_t)i0;
-                    const CURAST_GLOBAL float* q1 = gl(mesh.pos) + 3 * (size_t)i1;
-                    const CURAST_GLOBAL float* q2 = gl(mesh.pos) + 3 * (size_t)i2;
-                    p[0] = q0[0]; p[1] = q0[1]; p[2] = q0[2];
-                    p[3] = q1[0]; p[4] = q1[1]; p[5] = q1[2];
-                    p[6] = q2[0]; p[7] = q2[1]; p[8] = q2[2];
+#pragma unroll
+                    for (int v = 0; v < 3; ++v) {
+                        float q[3];
+                        mesh_vertex(mesh, iv[v], q);
+                        p[3 * v] = q[0];
+                        p[3 * v + 1] = q[1];
+                        p[3 * v + 2] = q[2];
+                    }
                 }
             }
 #pragma unroll 1
@@ -530,10 +532,12 @@ __device__ __forceinline__ void drain_ring(const RasterArgs& a, const ViewDesc* 
         tt = e.tri;
         const DrawDesc& D = d_draws[dd];
         const MeshDesc& M = d_meshes[e.mesh];
-        const CURAST_GLOBAL uint32_t* ip = gl(M.idx) + 3 * (uint64_t)tt;
+        uint32_t iv[3];
+        mesh_triangle(M, tt, iv);
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            const CURAST_GLOBAL float* q = gl(M.pos) + 3 * (size_t)ip[k];
+            float q[3];
+            mesh_vertex(M, iv[k], q);
             c[k] = transform(D.A, q[0], q[1], q[2]);
         }
         V = d_views[D.view & kDrawViewMask];
@@ -603,7 +607,7 @@ __device__ __forceinline__ bool fast_reject_union(const float2 (&w)[N], const Vi
     return fast_reject_extent(x0, x1, y0, y1, V, tiny_cull);
 }
 
-template <int BLOCK, int TPT, bool STRIPS, bool STATS>
+template <int BLOCK, int TPT, bool STRIPS, bool STATS, int CMP>
 __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST_DESC_PARAMS)
 {
     static_assert(!STRIPS || TPT == 2 || TPT == 4, "strips of 2 or 4 triangles per lane");
@@ -671,10 +675,7 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                                (STRIPS ? (uint64_t)(threadIdx.x * TPT + k) : (uint64_t)(k * BLOCK + threadIdx.x));
             tri[k] = (uint32_t)t;
             valid[k] = t < mesh.T;
-            const CURAST_GLOBAL uint32_t* ip = gl(mesh.idx) + 3 * (valid[k] ? t : 0);
-            vi[k][0] = ip[0];
-            vi[k][1] = ip[1];
-            vi[k][2] = ip[2];
+            mesh_triangle<CMP>(mesh, valid[k] ? t : 0, vi[k]);
         }
 #pragma unroll
         for (int k = 0; k < TPT; ++k)
@@ -696,10 +697,7 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                 float q[TPT + 2][3];
 #pragma unroll
                 for (int i = 0; i < TPT + 2; ++i) {
-                    const CURAST_GLOBAL float* src = gl(mesh.pos) + 3 * (size_t)(any_valid ? sv[i] : 0u);
-                    q[i][0] = src[0];
-                    q[i][1] = src[1];
-                    q[i][2] = src[2];
+                    mesh_vertex<CMP>(mesh, any_valid ? sv[i] : 0u, q[i]);
                 }
 #pragma unroll 1
                 for (uint32_t d = d0; d < d1; ++d) {
@@ -754,7 +752,8 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                 float p[9];
 #pragma unroll
                 for (int v = 0; v < 3; ++v) {
-                    const CURAST_GLOBAL float* src = gl(mesh.pos) + 3 * (size_t)(vk ? i3[v] : 0u);
+                    float src[3];
+                    mesh_vertex<CMP>(mesh, vk ? i3[v] : 0u, src);
                     p[3 * v + 0] = src[0];
                     p[3 * v + 1] = src[1];
                     p[3 * v + 2] = src[2];
@@ -779,7 +778,8 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
             for (int k = 0; k < TPT; ++k)
 #pragma unroll
                 for (int v = 0; v < 3; ++v) {
-                    const CURAST_GLOBAL float* src = gl(mesh.pos) + 3 * (size_t)(valid[k] ? vi[k][v] : 0u);
+                    float src[3];
+                    mesh_vertex<CMP>(mesh, valid[k] ? vi[k][v] : 0u, src);
                     p[k][3 * v + 0] = src[0];
                     p[k][3 * v + 1] = src[1];
                     p[k][3 * v + 2] = src[2];
@@ -879,10 +879,7 @@ __global__ void __launch_bounds__(64) stage1_share_kernel(RasterArgs a, CURAST_D
             const uint64_t t = tb * (uint64_t)NT + (uint64_t)(k * 64) + lane;
             tri[k] = (uint32_t)t;
             valid[k] = t < mesh.T;
-            const CURAST_GLOBAL uint32_t* ip = gl(mesh.idx) + 3 * (valid[k] ? t : 0);
-            vi[k][0] = ip[0];
-            vi[k][1] = ip[1];
-            vi[k][2] = ip[2];
+            mesh_triangle(mesh, valid[k] ? t : 0, vi[k]);
         }
         for (int i = lane; i < HT; i += 64) s_key[i] = kFree;
         if (lane == 0) s_nu = 0;
@@ -924,10 +921,7 @@ __global__ void __launch_bounds__(64) stage1_share_kernel(RasterArgs a, CURAST_D
 #pragma unroll
         for (int r = 0; r < RS; ++r) {
             const uint32_t u = lane + 64 * r;
-            const CURAST_GLOBAL float* q = gl(mesh.pos) + 3 * (size_t)(u < nu ? s_uniq[u] : 0u);
-            pu[r][0] = q[0];
-            pu[r][1] = q[1];
-            pu[r][2] = q[2];
+            mesh_vertex(mesh, u < nu ? s_uniq[u] : 0u, pu[r]);
         }
 #pragma unroll 1
         for (uint32_t d = d0; d < d1; ++d) {
@@ -1002,14 +996,17 @@ __global__ void __launch_bounds__(256) stage1_overflow_kernel(RasterArgs a, CURA
         for (uint32_t tt = threadIdx.x; tt < bt; tt += blockDim.x) {
             const uint64_t t = tb * bt + tt;
             if (t >= mesh.T) break;
-            const uint32_t i0 = mesh.idx[3 * t], i1 = mesh.idx[3 * t + 1], i2 = mesh.idx[3 * t + 2];
-            if (i0 >= mesh.V || i1 >= mesh.V || i2 >= mesh.V) continue;
+            uint32_t iv[3];
+            mesh_triangle(mesh, t, iv);
+            if (iv[0] >= mesh.V || iv[1] >= mesh.V || iv[2] >= mesh.V) continue;
+            float p[3][3];
+#pragma unroll
+            for (int k = 0; k < 3; ++k) mesh_vertex(mesh, iv[k], p[k]);
             for (uint32_t d = d0; d < d1; ++d) {
                 const DrawDesc D = d_draws[d];
                 const ViewDesc V = d_views[D.view & kDrawViewMask];
-                const Clip c[3] = {transform(D.A, mesh.pos[3 * (size_t)i0], mesh.pos[3 * (size_t)i0 + 1], mesh.pos[3 * (size_t)i0 + 2]),
-                                   transform(D.A, mesh.pos[3 * (size_t)i1], mesh.pos[3 * (size_t)i1 + 1], mesh.pos[3 * (size_t)i1 + 2]),
-                                   transform(D.A, mesh.pos[3 * (size_t)i2], mesh.pos[3 * (size_t)i2 + 1], mesh.pos[3 * (size_t)i2 + 2])};
+                const Clip c[3] = {transform(D.A, p[0][0], p[0][1], p[0][2]), transform(D.A, p[1][0], p[1][1], p[1][2]),
+                                   transform(D.A, p[2][0], p[2][1], p[2][2])};
                 SmallTri s;
                 if (classify<false>(c, V, a.small_px, tiny_cull, s, st) == kRouteForward)
                     raster_any_thread(c, D.id_base + t, V, early_out);
@@ -1039,9 +1036,12 @@ __global__ void __launch_bounds__(256) stage2_kernel(RasterArgs a)
         const MeshDesc M = a.meshes[D.mesh];
         const uint64_t id = D.id_base + t;
         Clip c[3];
+        uint32_t iv[3];
+        mesh_triangle(M, t, iv);
         for (int k = 0; k < 3; ++k) {
-            const uint32_t vi = M.idx[3 * (uint64_t)t + k];
-            c[k] = transform(D.A, M.pos[3 * (size_t)vi], M.pos[3 * (size_t)vi + 1], M.pos[3 * (size_t)vi + 2]);
+            float q[3];
+            mesh_vertex(M, iv[k], q);
+            c[k] = transform(D.A, q[0], q[1], q[2]);
         }
         Clip poly[8];
         int np = 3;
@@ -1303,11 +1303,18 @@ hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool
     }
 }
 
+// Launches whose meshes are all plain use the kernel without the per-mesh compression branch.
 template <int BLOCK, int TPT, bool STRIPS>
 static hipError_t stage1_fast_dispatch(const RasterArgs& a, bool stats, uint32_t grid, hipStream_t s)
 {
-    if (stats) stage1_fast_kernel<BLOCK, TPT, STRIPS, true><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
-    else stage1_fast_kernel<BLOCK, TPT, STRIPS, false><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    const bool cmp = (a.compressed_parts >> a.part) & 1u;
+    if (cmp) {
+        if (stats) stage1_fast_kernel<BLOCK, TPT, STRIPS, true, -1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+        else stage1_fast_kernel<BLOCK, TPT, STRIPS, false, -1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    } else {
+        if (stats) stage1_fast_kernel<BLOCK, TPT, STRIPS, true, 0><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+        else stage1_fast_kernel<BLOCK, TPT, STRIPS, false, 0><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    }
     return hipGetLastError();
 }
 

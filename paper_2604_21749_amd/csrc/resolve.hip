@@ -57,8 +57,7 @@ __device__ __forceinline__ void write_zero(uint32_t C, float* o)
 // Window positions of one mesh instance: pos_ss[v] = (sx, sy, w) before snapping
 // ----------------------------------------------------------------------------------------------
 struct ProjectArgs {
-    const float* pos;
-    uint32_t V;
+    MeshDesc mesh;                // plain or compressed positions
     float A[12];
     float hW, hH;
     float* out;
@@ -67,8 +66,10 @@ struct ProjectArgs {
 __global__ void __launch_bounds__(256) project_kernel(ProjectArgs a)
 {
     const uint64_t v = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= a.V) return;
-    const Clip c = transform(a.A, a.pos[3 * v], a.pos[3 * v + 1], a.pos[3 * v + 2]);
+    if (v >= a.mesh.V) return;
+    float p[3];
+    mesh_vertex(a.mesh, (uint32_t)v, p);
+    const Clip c = transform(a.A, p[0], p[1], p[2]);
     const float zI = 1.0f / c.w;
     a.out[3 * v + 0] = __builtin_fmaf(c.x * zI, a.hW, a.hW);
     a.out[3 * v + 1] = __builtin_fmaf(c.y * zI, a.hH, a.hH);
@@ -80,29 +81,21 @@ __global__ void __launch_bounds__(256) project_kernel(ProjectArgs a)
 // ----------------------------------------------------------------------------------------------
 constexpr uint32_t kLdsBases = 2048;   // prefix entries staged in LDS for the binary search
 
-__global__ void __launch_bounds__(256) resolve_kernel(ResolveArgs a, const uint64_t* __restrict__ bases,
-                                                      const DrawDesc* __restrict__ pairs,
-                                                      const MeshDesc* __restrict__ meshes,
-                                                      const float* const* __restrict__ attrs)
+// The triangle of pixel p of the view (row-major index) and its interpolation weights there;
+// false for an empty pixel or an invalid triangle.
+struct PixelHit {
+    const float* a[3];   // attribute rows of the three vertices
+    float b[3];
+};
+
+__device__ __forceinline__ bool resolve_hit(const ResolveArgs& a, const uint64_t* B, const DrawDesc* __restrict__ pairs,
+                                            const MeshDesc* __restrict__ meshes, const float* const* __restrict__ attrs,
+                                            uint64_t p, PixelHit& h)
 {
-    __shared__ uint64_t s_bases[kLdsBases + 1];
     const uint32_t np = a.n_pairs;
-    const bool staged = np <= kLdsBases;
-    if (staged) {
-        for (uint32_t i = threadIdx.x; i <= np; i += blockDim.x) s_bases[i] = bases[i];
-        __syncthreads();
-    }
-    const uint64_t* B = staged ? s_bases : bases;
-    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const uint64_t npix = (uint64_t)a.W * (uint64_t)a.H;
-    if (p >= npix) return;
-    float* o = a.out + p * a.C;
     const unsigned long long key = gl(a.vis)[p];
     const uint64_t id = key & kIdMask;
-    if (key == kEmptyKey || id >= B[np]) {
-        write_zero(a.C, o);
-        return;
-    }
+    if (key == kEmptyKey || id >= B[np]) return false;
     uint32_t lo = 0, hi = np;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
@@ -112,16 +105,14 @@ __global__ void __launch_bounds__(256) resolve_kernel(ResolveArgs a, const uint6
     const DrawDesc& D = pairs[lo];
     const MeshDesc& M = meshes[D.mesh];
     const uint64_t t = id - B[lo];
-    const CURAST_GLOBAL uint32_t* ip = gl(M.idx) + 3 * t;
-    const uint32_t vi[3] = {ip[0], ip[1], ip[2]};
-    if (vi[0] >= M.V || vi[1] >= M.V || vi[2] >= M.V) {
-        write_zero(a.C, o);
-        return;
-    }
+    uint32_t vi[3];
+    mesh_triangle(M, t, vi);
+    if (vi[0] >= M.V || vi[1] >= M.V || vi[2] >= M.V) return false;
     float sx[3], sy[3], w[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        const CURAST_GLOBAL float* q = gl(M.pos) + 3 * (size_t)vi[k];
+        float q[3];
+        mesh_vertex(M, vi[k], q);
         const Clip c = transform(D.A, q[0], q[1], q[2]);
         const float zI = 1.0f / c.w;
         sx[k] = __builtin_fmaf(c.x * zI, a.hW, a.hW);
@@ -132,7 +123,79 @@ __global__ void __launch_bounds__(256) resolve_kernel(ResolveArgs a, const uint6
     Interp r;
     interp_weights(sx, sy, w, px, py, r);
     const float* at = attrs[D.mesh];
-    write_interp(r, at + (size_t)vi[0] * a.C, at + (size_t)vi[1] * a.C, at + (size_t)vi[2] * a.C, a.C, o);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        h.a[k] = at + (size_t)vi[k] * a.C;
+        h.b[k] = r.b[k];
+    }
+    return true;
+}
+
+// Stage the prefix of triangle counts in LDS when it fits (all threads of the block take part).
+__device__ __forceinline__ const uint64_t* stage_bases(const ResolveArgs& a, const uint64_t* __restrict__ bases,
+                                                       uint64_t* s_bases)
+{
+    const bool staged = a.n_pairs <= kLdsBases;
+    if (staged) {
+        for (uint32_t i = threadIdx.x; i <= a.n_pairs; i += blockDim.x) s_bases[i] = bases[i];
+        __syncthreads();
+    }
+    return staged ? s_bases : bases;
+}
+
+__global__ void __launch_bounds__(256) resolve_kernel(ResolveArgs a, const uint64_t* __restrict__ bases,
+                                                      const DrawDesc* __restrict__ pairs,
+                                                      const MeshDesc* __restrict__ meshes,
+                                                      const float* const* __restrict__ attrs)
+{
+    __shared__ uint64_t s_bases[kLdsBases + 1];
+    const uint64_t* B = stage_bases(a, bases, s_bases);
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t npix = (uint64_t)a.W * (uint64_t)a.H;
+    if (p >= npix) return;
+    float* o = a.out + p * a.C;
+    PixelHit h;
+    if (!resolve_hit(a, B, pairs, meshes, attrs, p, h)) {
+        write_zero(a.C, o);
+        return;
+    }
+    for (uint32_t c = 0; c < a.C; ++c) o[c] = (h.b[0] * h.a[0][c] + h.b[1] * h.a[1][c]) + h.b[2] * h.a[2][c];
+}
+
+// Supersampled resolve: the view holds ss x ss samples per output pixel (a visibility buffer of
+// ss W_out x ss H_out); each lane resolves the samples of one output pixel, sums them in fp32 row
+// by row (empty samples add 0) and scales by 1 / ss^2 (exact).
+constexpr uint32_t kMaxChannels = 16;
+
+__global__ void __launch_bounds__(256) resolve_ss_kernel(ResolveArgs a, const uint64_t* __restrict__ bases,
+                                                         const DrawDesc* __restrict__ pairs,
+                                                         const MeshDesc* __restrict__ meshes,
+                                                         const float* const* __restrict__ attrs)
+{
+    __shared__ uint64_t s_bases[kLdsBases + 1];
+    const uint64_t* B = stage_bases(a, bases, s_bases);
+    const uint32_t k = a.ss;
+    const uint32_t Wo = (uint32_t)a.W / k, Ho = (uint32_t)a.H / k;
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (uint64_t)Wo * Ho) return;
+    const uint32_t px = (uint32_t)(p % Wo), py = (uint32_t)(p / Wo);
+    float acc[kMaxChannels];
+#pragma unroll
+    for (uint32_t c = 0; c < kMaxChannels; ++c) acc[c] = 0.0f;
+    for (uint32_t sy = 0; sy < k; ++sy)
+        for (uint32_t sx = 0; sx < k; ++sx) {
+            const uint64_t q = (uint64_t)(py * k + sy) * (uint64_t)a.W + (px * k + sx);
+            PixelHit h;
+            if (!resolve_hit(a, B, pairs, meshes, attrs, q, h)) continue;
+#pragma unroll
+            for (uint32_t c = 0; c < kMaxChannels; ++c)
+                if (c < a.C) acc[c] += (h.b[0] * h.a[0][c] + h.b[1] * h.a[1][c]) + h.b[2] * h.a[2][c];
+        }
+    const float scale = 1.0f / (float)(k * k);
+    float* o = a.out + p * a.C;
+#pragma unroll
+    for (uint32_t c = 0; c < kMaxChannels; ++c)
+        if (c < a.C) o[c] = acc[c] * scale;
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -232,23 +295,28 @@ __global__ void __launch_bounds__(256) resolve_backward_kernel(ScreenArgs a)
 // ----------------------------------------------------------------------------------------------
 static uint32_t blocks_for(uint64_t n) { return (uint32_t)((n + 255) / 256); }
 
-hipError_t launch_project(const float* pos, uint32_t V, const float A[12], float hW, float hH, float* out, hipStream_t s)
+hipError_t launch_project(const MeshDesc& mesh, const float A[12], float hW, float hH, float* out, hipStream_t s)
 {
     ProjectArgs a;
-    a.pos = pos;
-    a.V = V;
+    a.mesh = mesh;
     for (int i = 0; i < 12; ++i) a.A[i] = A[i];
     a.hW = hW;
     a.hH = hH;
     a.out = out;
-    if (V == 0) return hipSuccess;
-    project_kernel<<<blocks_for(V), 256, 0, s>>>(a);
+    if (mesh.V == 0) return hipSuccess;
+    project_kernel<<<blocks_for(mesh.V), 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
 hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s)
 {
-    resolve_kernel<<<blocks_for((uint64_t)a.W * (uint64_t)a.H), 256, 0, s>>>(a, a.bases, a.pairs, a.meshes, a.attrs);
+    if (a.ss > 1) {
+        const uint64_t out_pixels = (uint64_t)(a.W / a.ss) * (uint64_t)(a.H / a.ss);
+        resolve_ss_kernel<<<blocks_for(out_pixels), 256, 0, s>>>(a, a.bases, a.pairs, a.meshes, a.attrs);
+    } else {
+        resolve_kernel<<<blocks_for((uint64_t)a.W * (uint64_t)a.H), 256, 0, s>>>(a, a.bases, a.pairs, a.meshes,
+                                                                                 a.attrs);
+    }
     return hipGetLastError();
 }
 

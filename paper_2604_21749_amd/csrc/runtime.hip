@@ -31,7 +31,12 @@ hipError_t launch_stage1_overflow(const RasterArgs& a, uint32_t grid, hipStream_
 hipError_t launch_stage2(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
 hipError_t launch_stage3(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
 hipError_t launch_stage3_binned(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
-hipError_t launch_project(const float* pos, uint32_t V, const float A[12], float hW, float hH, float* out, hipStream_t s);
+hipError_t launch_project(const MeshDesc& mesh, const float A[12], float hW, float hH, float* out, hipStream_t s);
+hipError_t launch_compress_ranges(const uint32_t* idx, uint64_t n_idx, const float* pos, uint32_t V, uint32_t* out,
+                                  uint32_t cus, hipStream_t s);
+hipError_t launch_compress(const uint32_t* idx, uint64_t n_idx, uint32_t bits, uint32_t base, uint32_t* packed,
+                           uint64_t words, const float* pos, uint32_t V, const float lo[3], const float scale[3],
+                           uint16_t* qpos, hipStream_t s);
 hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s);
 hipError_t launch_resolve_screen(const ScreenArgs& a, hipStream_t s);
 hipError_t launch_resolve_backward(const ScreenArgs& a, hipStream_t s);
@@ -95,6 +100,7 @@ struct curast_ctx {
     double stage_ms[kNumSlots] = {0};
     uint64_t timed_frames = 0;
     uint64_t draws_culled = 0;
+    uint32_t* ranges = nullptr;   // [8] index range and bounding box of curast_compress_prepare
 };
 
 namespace {
@@ -379,8 +385,17 @@ int check_view(curast_ctx* ctx, const curast_view& v, bool need_vis = true)
 int check_mesh(curast_ctx* ctx, const curast_mesh& m)
 {
     if (m.num_triangles > 0xFFFFFFFFull) return fail(ctx, CURAST_E_INVALID, "a mesh may hold at most 2^32-1 triangles");
-    if (m.num_triangles && (!m.vertices || !m.indices || m.num_vertices == 0))
+    if (m.compressed) {
+        const curast_compressed& c = *m.compressed;
+        if (m.num_triangles && (!c.indices || !c.positions || m.num_vertices == 0))
+            return fail(ctx, CURAST_E_INVALID, "compressed mesh with triangles needs packed indices and positions");
+        if (c.index_bits < 1 || c.index_bits > 32) return fail(ctx, CURAST_E_INVALID, "index_bits must lie in [1, 32]");
+        for (int k = 0; k < 3; ++k)
+            if (!std::isfinite(c.lo[k]) || !std::isfinite(c.step[k]) || c.step[k] < 0.0f)
+                return fail(ctx, CURAST_E_INVALID, "compressed lo / step must be finite, step >= 0");
+    } else if (m.num_triangles && (!m.vertices || !m.indices || m.num_vertices == 0)) {
         return fail(ctx, CURAST_E_INVALID, "mesh with triangles needs vertices and indices");
+    }
     if (m.instances && m.num_instances == 0) return fail(ctx, CURAST_E_INVALID, "instances given with num_instances == 0");
     if (m.instances)
         for (uint64_t i = 0; i < 12ull * m.num_instances; ++i)
@@ -389,6 +404,29 @@ int check_mesh(curast_ctx* ctx, const curast_mesh& m)
 }
 
 uint32_t n_inst(const curast_mesh& m) { return m.instances ? m.num_instances : 1u; }
+
+// Device descriptor of a mesh's geometry, plain or compressed.
+MeshDesc mesh_desc(const curast_mesh& m)
+{
+    MeshDesc d{};
+    d.T = m.num_triangles;
+    d.V = m.num_vertices;
+    if (m.compressed) {
+        const curast_compressed& c = *m.compressed;
+        d.idx = c.indices;
+        d.qpos = c.positions;
+        d.idx_bits = c.index_bits;
+        d.idx_min = c.index_min;
+        for (int k = 0; k < 3; ++k) {
+            d.lo[k] = c.lo[k];
+            d.step[k] = c.step[k];
+        }
+    } else {
+        d.pos = m.vertices;
+        d.idx = m.indices;
+    }
+    return d;
+}
 
 struct Plan {
     FrameHeader hdr{};
@@ -401,6 +439,7 @@ struct Plan {
     uint64_t total_pixels = 0;
     uint64_t max_batches = 0;        // without any culling (graph grid bound)
     uint64_t pair_count = 0;
+    bool compressed = false;         // some mesh is compressed (stage 1 then decodes per mesh)
     size_t max_draws = 0;            // without any culling
     size_t off_views = 0, off_meshes = 0, off_segs = 0, off_draws = 0, bytes = 0, max_bytes = 0;
 };
@@ -451,12 +490,8 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
     std::vector<uint32_t> mesh_draw_begin(M), mesh_draw_count(M);
     for (uint32_t m = 0; m < M; ++m) {
         const curast_mesh& me = meshes[m];
-        MeshDesc& md = P.meshes[m];
-        md.pos = me.vertices;
-        md.idx = me.indices;
-        md.T = me.num_triangles;
-        md.V = me.num_vertices;
-        md.pad = 0;
+        P.meshes[m] = mesh_desc(me);
+        P.compressed |= me.compressed != nullptr;
         const uint32_t ni = n_inst(me);
         const uint32_t draw_begin = (uint32_t)P.draws.size();
         for (uint32_t i = 0; i < ni; ++i, base += me.num_triangles) {
@@ -564,6 +599,7 @@ RasterArgs make_args(curast_ctx* ctx, const Plan& P)
     a.tile_count = ctx->tile_count;
     a.tile_offset = ctx->tile_offset;
     a.q3_binned = ctx->q3_binned;
+    a.compressed_parts = P.compressed ? 0x6u : 0u;
     return a;
 }
 
@@ -664,7 +700,7 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
                        ((uint64_t)ctx->opt.s1_block << 32) | (ctx->opt.s1_tris_per_thread << 8) |
                            (ctx->opt.s1_multi_tris_per_thread << 4) | ctx->opt.s1_mode,
                        ((uint64_t)ctx->opt.s2_waves << 32) | ctx->opt.s3_blocks,
-                       ((uint64_t)ctx->opt.flags << 32) | ctx->opt.small_px,
+                       ((uint64_t)ctx->opt.flags << 32) | ((uint64_t)P.compressed << 31) | ctx->opt.small_px,
                        ((uint64_t)ctx->opt.medium_px << 32) | ctx->opt.s1_draws_per_item};
     GraphEntry* ge = nullptr;
     for (auto& g : ctx->graphs)
@@ -750,11 +786,7 @@ int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, c
     const float** ap = reinterpret_cast<const float**>(h + off_attrs);
     uint64_t base = 0, p = 0;
     for (uint32_t m = 0; m < M; ++m) {
-        md[m].pos = meshes[m].vertices;
-        md[m].idx = meshes[m].indices;
-        md[m].T = meshes[m].num_triangles;
-        md[m].V = meshes[m].num_vertices;
-        md[m].pad = 0;
+        md[m] = mesh_desc(meshes[m]);
         ap[m] = attrs[m];
         for (uint32_t i = 0; i < n_inst(meshes[m]); ++i, ++p) {
             bases[p] = base;
@@ -867,6 +899,7 @@ int curast_destroy(curast_ctx* ctx)
     if (ctx->large) hipFree(ctx->large);
     if (ctx->counters) hipFree(ctx->counters);
     if (ctx->stats) hipFree(ctx->stats);
+    if (ctx->ranges) hipFree(ctx->ranges);
     if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
     delete ctx;
     return CURAST_OK;
@@ -935,23 +968,28 @@ int curast_project(curast_ctx* ctx, const curast_mesh* mesh, uint32_t instance, 
     rc = check_mesh(ctx, *mesh);
     if (rc) return rc;
     if (instance >= n_inst(*mesh)) return fail(ctx, CURAST_E_INVALID, "instance out of range");
-    if (mesh->num_vertices && !mesh->vertices) return fail(ctx, CURAST_E_INVALID, "vertices is NULL");
+    if (mesh->num_vertices && !mesh->vertices && !mesh->compressed)
+        return fail(ctx, CURAST_E_INVALID, "vertices is NULL");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     float A[12];
     draw_matrix(view->view_proj, mesh->instances ? mesh->instances + 12ull * instance : nullptr, A);
-    HIP_TRY(ctx, launch_project(mesh->vertices, mesh->num_vertices, A, 0.5f * (float)view->width,
+    HIP_TRY(ctx, launch_project(mesh_desc(*mesh), A, 0.5f * (float)view->width,
                                 0.5f * (float)view->height, pos_ss, static_cast<hipStream_t>(stream)));
     return CURAST_OK;
 }
 
-int curast_resolve(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* view,
-                   const float* const* attrs, uint32_t C, float* out, void* stream)
+namespace {
+int resolve_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* view,
+                 const float* const* attrs, uint32_t C, float* out, uint32_t ss, void* stream)
 {
     if (!ctx) return CURAST_E_INVALID;
     if (!view || !out || (M && (!meshes || !attrs))) return fail(ctx, CURAST_E_INVALID, "NULL pointer argument");
     if (C < 1 || C > 16) return fail(ctx, CURAST_E_INVALID, "C must lie in [1, 16]");
+    if (ss != 1 && ss != 2 && ss != 4) return fail(ctx, CURAST_E_INVALID, "samples per axis must be 1, 2 or 4");
     int rc = check_view(ctx, *view);
     if (rc) return rc;
+    if (view->width % (int32_t)ss || view->height % (int32_t)ss)
+        return fail(ctx, CURAST_E_INVALID, "view size must be a multiple of the samples per axis");
     uint64_t total = 0;
     for (uint32_t m = 0; m < M; ++m) {
         rc = check_mesh(ctx, meshes[m]);
@@ -968,6 +1006,7 @@ int curast_resolve(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
     if (rc) return rc;
     a.C = C;
     a.out = out;
+    a.ss = ss;
     HIP_TRY(ctx, hipMemcpyAsync(ctx->resolve_stage.dev, ctx->resolve_stage.host, bytes, hipMemcpyHostToDevice, s));
     HIP_TRY(ctx, hipEventRecord(ctx->resolve_stage.ev, s));
     ctx->resolve_stage.pending = true;
@@ -978,6 +1017,94 @@ int curast_resolve(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
         hipEventRecord(tf->ev[8], s);
         tf->used[kTResolve] = 1;
     }
+    return CURAST_OK;
+}
+}  // namespace
+
+int curast_resolve(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* view,
+                   const float* const* attrs, uint32_t C, float* out, void* stream)
+{
+    return resolve_impl(ctx, meshes, M, view, attrs, C, out, 1, stream);
+}
+
+int curast_resolve_supersampled(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* view,
+                                uint32_t samples_per_axis, const float* const* attrs, uint32_t C, float* out,
+                                void* stream)
+{
+    return resolve_impl(ctx, meshes, M, view, attrs, C, out, samples_per_axis, stream);
+}
+
+namespace {
+int check_plain_mesh(curast_ctx* ctx, const curast_mesh* mesh)
+{
+    if (!mesh) return fail(ctx, CURAST_E_INVALID, "mesh is NULL");
+    if (mesh->compressed) return fail(ctx, CURAST_E_INVALID, "the mesh to compress must be uncompressed");
+    int rc = check_mesh(ctx, *mesh);
+    if (rc) return rc;
+    if (mesh->num_vertices && !mesh->vertices) return fail(ctx, CURAST_E_INVALID, "vertices is NULL");
+    return CURAST_OK;
+}
+
+// Inverse of the device's order-preserving map of binary32 to uint32.
+float binary32_of_ordered(uint32_t o)
+{
+    const uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+    float f;
+    std::memcpy(&f, &u, sizeof f);
+    return f;
+}
+
+// Quantization scale of an axis from its step: the rounded reciprocal, 0 for a flat axis.
+float quant_scale(float step) { return step > 0.0f ? (float)(1.0 / (double)step) : 0.0f; }
+}  // namespace
+
+int curast_compress_prepare(curast_ctx* ctx, const curast_mesh* mesh, curast_compressed* info, uint64_t* index_words,
+                            void* stream)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    if (!info || !index_words) return fail(ctx, CURAST_E_INVALID, "NULL pointer argument");
+    int rc = check_plain_mesh(ctx, mesh);
+    if (rc) return rc;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!ctx->ranges) HIP_TRY(ctx, hipMalloc(&ctx->ranges, 8 * sizeof(uint32_t)));
+    const uint64_t n_idx = 3ull * mesh->num_triangles;
+    HIP_TRY(ctx, launch_compress_ranges(mesh->indices, n_idx, mesh->vertices, mesh->num_vertices, ctx->ranges,
+                                        (uint32_t)ctx->cus, s));
+    uint32_t r[8];
+    HIP_TRY(ctx, hipMemcpyAsync(r, ctx->ranges, sizeof r, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    const uint32_t imin = n_idx ? r[0] : 0u, imax = n_idx ? r[1] : 0u;
+    const uint32_t span = imax - imin;
+    info->index_min = imin;
+    info->index_bits = span ? 32u - (uint32_t)__builtin_clz(span) : 1u;
+    for (int c = 0; c < 3; ++c) {
+        const float lo = mesh->num_vertices ? binary32_of_ordered(r[2 + c]) : 0.0f;
+        const float hi = mesh->num_vertices ? binary32_of_ordered(r[5 + c]) : 0.0f;
+        if (!std::isfinite(lo) || !std::isfinite(hi)) return fail(ctx, CURAST_E_INVALID, "positions must be finite");
+        info->lo[c] = lo;
+        info->step[c] = (float)(((double)hi - (double)lo) / 65535.0);
+    }
+    *index_words = (n_idx * info->index_bits + 31) / 32 + 1;
+    return CURAST_OK;
+}
+
+int curast_compress(curast_ctx* ctx, const curast_mesh* mesh, const curast_compressed* info, uint32_t* packed_indices,
+                    uint16_t* positions, void* stream)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    if (!info || (mesh && !packed_indices) || (mesh && mesh->num_vertices && !positions))
+        return fail(ctx, CURAST_E_INVALID, "NULL pointer argument");
+    int rc = check_plain_mesh(ctx, mesh);
+    if (rc) return rc;
+    if (info->index_bits < 1 || info->index_bits > 32) return fail(ctx, CURAST_E_INVALID, "index_bits must lie in [1, 32]");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    const uint64_t n_idx = 3ull * mesh->num_triangles;
+    const uint64_t words = (n_idx * info->index_bits + 31) / 32 + 1;
+    const float scale[3] = {quant_scale(info->step[0]), quant_scale(info->step[1]), quant_scale(info->step[2])};
+    HIP_TRY(ctx, launch_compress(mesh->indices, n_idx, info->index_bits, info->index_min, packed_indices, words,
+                                 mesh->vertices, mesh->num_vertices, info->lo, scale, positions,
+                                 static_cast<hipStream_t>(stream)));
     return CURAST_OK;
 }
 

@@ -56,6 +56,8 @@ def test_struct_layouts_match_the_binding(api):
 int main(void) {
   P(curast_options); O(curast_options, flags); O(curast_options, s1_mode);
   P(curast_mesh); O(curast_mesh, num_triangles); O(curast_mesh, instances); O(curast_mesh, bsphere);
+  O(curast_mesh, compressed);
+  P(curast_compressed); O(curast_compressed, index_min); O(curast_compressed, lo); O(curast_compressed, step);
   P(curast_view); O(curast_view, near_plane); O(curast_view, visbuffer);
   P(curast_stats); O(curast_stats, atomics);
   return 0;
@@ -76,6 +78,10 @@ int main(void) {
     assert got["curast_mesh.num_triangles"] == api.MeshStruct.num_triangles.offset
     assert got["curast_mesh.instances"] == api.MeshStruct.instances.offset
     assert got["curast_mesh.bsphere"] == api.MeshStruct.bsphere.offset
+    assert got["curast_mesh.compressed"] == api.MeshStruct.compressed.offset
+    assert got["curast_compressed"] == C.sizeof(api.CompressedStruct)
+    for f in ("index_min", "lo", "step"):
+        assert got[f"curast_compressed.{f}"] == getattr(api.CompressedStruct, f).offset
     assert got["curast_view"] == C.sizeof(api.ViewStruct)
     assert got["curast_view.near_plane"] == api.ViewStruct.near_plane.offset
     assert got["curast_view.visbuffer"] == api.ViewStruct.visbuffer.offset
@@ -102,6 +108,9 @@ def test_null_context_is_rejected_without_a_gpu(api):
     assert L.curast_rasterize_batched(None, None, 0, None, 0, None) == api.E_INVALID
     assert L.curast_project(None, None, 0, None, None, None) == api.E_INVALID
     assert L.curast_resolve(None, None, 0, None, None, 3, None, None) == api.E_INVALID
+    assert L.curast_resolve_supersampled(None, None, 0, None, 2, None, 3, None, None) == api.E_INVALID
+    assert L.curast_compress_prepare(None, None, None, None, None) == api.E_INVALID
+    assert L.curast_compress(None, None, None, None, None, None) == api.E_INVALID
     assert L.curast_resolve_screen(None, None, 8, 8, None, 0, 0, None, 1, None, 3, None, None) == api.E_INVALID
     assert L.curast_resolve_backward(None, None, 8, 8, None, 0, 0, None, 1, None, 3, None, None, None,
                                      None) == api.E_INVALID

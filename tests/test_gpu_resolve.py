@@ -87,3 +87,21 @@ def test_backward_small_scene_vs_fp64(ctx):
     ga2 = torch.zeros_like(g.attrs)
     ctx.resolve_backward(vis, g.idx, pss, g.attrs, torch.from_numpy(gout).cuda(), ga2, None, id_base=1 << 30)
     assert float(ga2.abs().sum()) == 0.0
+
+
+@pytest.mark.parametrize("k,size", [(1, 256), (2, 256), (4, 96)])
+def test_supersampled_resolve(ctx, k, size):
+    """curast_resolve_supersampled against the oracle's per-sample resolve and box filter, on the
+    C1 scene rasterized at k times the output size."""
+    s = W.scene_c1()
+    hi = W.View(s.views[0].vp, s.views[0].near, size * k, size * k)
+    gm = [api.GpuMesh.from_host(m) for m in s.meshes]
+    vis = ctx.rasterize_meshes(gm, hi)
+    ref_vis = O.rasterize(s.meshes, hi)
+    assert_vis_equal(api.as_uint64(vis), ref_vis, f"C1 at {k}x")
+    out = ctx.resolve(gm, hi, vis, [g.attrs for g in gm], samples_per_axis=k).cpu().numpy()
+    assert out.shape == (size, size, 3)
+    ref = O.resolve_supersampled(s.meshes, hi, ref_vis, [m.attrs for m in s.meshes], k)
+    assert_resolve_close(out, ref, f"supersampled resolve {k}x{k}")
+    if k == 1:
+        assert np.array_equal(out, ctx.resolve(gm, hi, vis, [g.attrs for g in gm]).cpu().numpy())

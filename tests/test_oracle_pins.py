@@ -421,6 +421,96 @@ def test_resolve_matches_world_space_ray_hit():
     assert worst < 1e-5
 
 
+def test_supersampled_resolve_pins():
+    """Supersampling (Sec. 5, Table 5) = rasterize at k times the resolution with the same
+    projection, resolve every sample, average k x k blocks.  Pins: k = 1 is the identity; a
+    constant attribute 1 gives the covered-sample fraction (each sample resolves to 1 within a few
+    ulp of the barycentric sum); on a fronto-parallel plane an
+    attribute affine in screen space averages over the symmetric sample grid to its value at the
+    pixel centre, i.e. the 1x resolve."""
+    Wd, Hd = 24, 20
+    vp = W.camera((0.0, 0.0, 0.0), (0.0, 0.0, -1.0), aspect=Wd / Hd)
+    # a triangle partly covering the view, one attribute row = 1
+    tri = np.array([[-0.9, -0.6, -2.0], [1.1, -0.4, -2.0], [0.1, 0.9, -2.0]], np.float32)
+    mesh = W.Mesh(tri, np.array([[0, 1, 2]], np.uint32))
+    ones = np.ones((3, 1), np.float32)
+    for k in (1, 2, 4):
+        hi = W.View(vp, 0.05, Wd * k, Hd * k)
+        vis = O.rasterize([mesh], hi)
+        out = O.resolve_supersampled([mesh], hi, vis, [ones], k)
+        cov = (vis != O.EMPTY).astype(np.float64).reshape(Hd, k, Wd, k).sum(axis=(1, 3)) / (k * k)
+        assert np.max(np.abs(out[..., 0].astype(np.float64) - cov)) <= 16 * 2.0 ** -24, k
+        assert cov.min() == 0 and cov.max() == 1 and (k == 1 or ((cov > 0) & (cov < 1)).sum() > 10)
+        if k == 1:
+            assert np.array_equal(out, O.resolve([mesh], hi, vis, [ones]))
+    # full-screen fronto-parallel quad at depth 2, attribute = a x_ndc + b y_ndc + c at its corners
+    f = 1.0 / np.tan(np.radians(W.FOVY_DEG) / 2.0)
+    X, Y = 2.0 * (Wd / Hd) / f * 1.5, 2.0 / f * 1.5
+    quad = np.array([[-X, -Y, -2.0], [X, -Y, -2.0], [X, Y, -2.0], [-X, Y, -2.0]], np.float32)
+    qidx = np.array([[0, 1, 2], [0, 2, 3]], np.uint32)
+    ndc = quad[:, :2].astype(np.float64) / np.array([X / 1.5, Y / 1.5])
+    attr = (0.3 * ndc[:, :1] - 0.2 * ndc[:, 1:] + 0.5).astype(np.float32)
+    plane = W.Mesh(quad, qidx)
+    lo = W.View(vp, 0.05, Wd, Hd)
+    ref = O.resolve([plane], lo, O.rasterize([plane], lo), [attr])
+    for k in (2, 4):
+        hi = W.View(vp, 0.05, Wd * k, Hd * k)
+        out = O.resolve_supersampled([plane], hi, O.rasterize([plane], hi), [attr], k)
+        assert np.max(np.abs(out - ref)) <= 1e-6, k
+
+
+# ----------------------------------------------------------------------------------------------
+# compressed geometry (Sec. 4.6)
+# ----------------------------------------------------------------------------------------------
+def test_index_width_matches_the_paper_example_and_boundaries():
+    g = json.load(open(os.path.join(GOLDEN, "compression_example.json")))
+    assert O.index_bits(g["index_max"] - g["index_min"]) == g["bits"]
+    idx = np.array([[2500, 2750, 3000], [2999, 2501, 2600]], np.uint32)
+    lo, bits, words = O.compress_indices(idx)
+    assert (lo, bits) == (2500, 9) and words.size == (6 * 9 + 31) // 32 + 1
+    # widths at powers of two: span 2^k - 1 needs k bits, span 2^k needs k + 1
+    for k in range(1, 32):
+        assert O.index_bits((1 << k) - 1) == k and O.index_bits(1 << k) == k + 1
+    assert O.index_bits(0) == 1 and O.index_bits(0xFFFFFFFF) == 32
+
+
+def test_index_packing_round_trip_and_layout():
+    rng = np.random.default_rng(21)
+    for b in (1, 2, 3, 7, 8, 9, 16, 17, 28, 31, 32):
+        span = (1 << b) - 1
+        base = 0 if b == 32 else int(rng.integers(0, (1 << 32) - 1 - span))
+        idx = (rng.integers(0, span, (41, 3), dtype=np.uint64, endpoint=True) + base).astype(np.uint32)
+        idx[0, 0], idx[5, 2] = base, base + span
+        lo, bits, words = O.compress_indices(idx)
+        assert (lo, bits) == (base, b)
+        assert np.array_equal(O.decompress_indices(words, lo, bits, 41), idx)
+        # little-endian bit stream: index i's lowest bit is bit (i b) % 32 of word (i b) / 32
+        flat = idx.reshape(-1).astype(np.uint64) - base
+        for i in (0, 1, 7, 122):
+            w, r = divmod(i * b, 32)
+            assert (int(words[w]) >> r) & 1 == int(flat[i]) & 1
+        assert words[-1] == 0 or words.size == 1
+
+
+def test_position_quantization_bounds():
+    rng = np.random.default_rng(22)
+    pos = rng.normal(0, 3, (500, 3)).astype(np.float32)
+    pos[:, 2] = 1.25                                  # a flat axis
+    lo, step = O.position_box(pos)
+    assert step[2] == 0 and np.all(step[:2] > 0)
+    q = O.quantize_positions(pos, lo, step)
+    dec = O.decode_positions(q, lo, step)
+    assert q[:, :2].min() == 0 and q[:, :2].max() == 65535
+    assert np.all(dec[:, 2] == 1.25)
+    # each decoded coordinate within half a step (plus binary32 rounding) of the original
+    err = np.abs(dec.astype(np.float64) - pos)[:, :2]
+    bound = 0.5 * step[:2].astype(np.float64) * (1 + 1e-6) + 4 * np.spacing(np.abs(pos[:, :2]).max())
+    assert np.all(err <= bound), (err.max(axis=0), bound)
+    # the box minimum decodes exactly, the maximum within one ulp
+    i0 = np.argmin(pos[:, 0])
+    assert q[i0, 0] == 0 and dec[i0, 0] == pos[i0, 0]
+
+
 # ----------------------------------------------------------------------------------------------
 # backward
 # ----------------------------------------------------------------------------------------------
