@@ -120,11 +120,16 @@ typedef struct {
  *                            little-endian bit stream `indices` (uint32 words, bit 0 first);
  *   position component c   = fmaf((float)positions[3 v + c], step[c], lo[c]).
  * curast_compress_prepare computes index_min, index_bits, lo and step; curast_compress fills the
- * two buffers.  The buffers are the caller's (device memory).
+ * two buffers.  The buffers are the caller's (device memory, 4-byte aligned).  Both carry
+ * padding that the decoders read past the last value (a triangle's indices are read with one
+ * load of up to four words, a vertex with one 8-byte load): three zero words after the index
+ * stream and one zero element after the positions.
  */
 typedef struct {
-    const uint32_t* indices;    /* device, curast_compress_prepare's index_words uint32 words */
-    const uint16_t* positions;  /* device [V][3] quantized positions */
+    const uint32_t* indices;    /* device, curast_compress_prepare's index_words uint32 words:
+                                   ceil(3 T index_bits / 32) words of stream + 3 of padding */
+    const uint16_t* positions;  /* device, 3 V + 1 elements: [V][3] quantized positions, then
+                                   one padding element */
     uint32_t index_min;         /* smallest index of the mesh */
     uint32_t index_bits;        /* ceil(log2(max - min + 1)), at least 1 and at most 32 */
     float lo[3];                /* bounding-box minimum */
@@ -225,15 +230,15 @@ int curast_project(curast_ctx* ctx, const curast_mesh* mesh, uint32_t instance,
  * Compression (Sec. 4.6), step 1: from the uncompressed mesh (vertices and indices set), the
  * smallest and largest index and the positions' bounding box, giving info->index_min,
  * index_bits, lo and step, and the size of the packed index stream in uint32 words
- * (ceil(3 T index_bits / 32) + 1).  Synchronizes the stream.  info->indices / positions are not
+ * (ceil(3 T index_bits / 32) + 3).  Synchronizes the stream.  info->indices / positions are not
  * touched.
  */
 int curast_compress_prepare(curast_ctx* ctx, const curast_mesh* mesh, curast_compressed* info,
                             uint64_t* index_words, void* stream);
 
 /*
- * Compression, step 2: writes the packed indices (index_words words, every bit defined) and the
- * quantized positions q = clamp(rint((p - lo) * scale), 0, 65535) with
+ * Compression, step 2: writes the packed indices (index_words words, every bit defined, the
+ * padding 0) and the 3 V + 1 position elements (the last one 0): quantized positions q = clamp(rint((p - lo) * scale), 0, 65535) with
  * scale = (float)(1.0 / (double)step) per axis (0 for a flat axis), the subtraction and product
  * in binary32, rint rounding half to even.
  */

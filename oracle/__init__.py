@@ -182,13 +182,13 @@ def index_bits(span: int) -> int:
 
 def compress_indices(idx: np.ndarray):
     """(index_min, bits, packed uint32 words): index i of the flattened [T, 3] array minus
-    index_min occupies bits [i bits, (i + 1) bits) of a little-endian stream, plus one word of
-    padding.  Written bit by bit (small meshes only)."""
+    index_min occupies bits [i bits, (i + 1) bits) of a little-endian stream, plus three zero
+    words of padding.  Written bit by bit (small meshes only)."""
     flat = np.ascontiguousarray(idx, np.uint32).reshape(-1).astype(np.uint64)
     lo = int(flat.min()) if flat.size else 0
     hi = int(flat.max()) if flat.size else 0
     b = index_bits(hi - lo)
-    words = np.zeros((flat.size * b + 31) // 32 + 1, np.uint64)
+    words = np.zeros((flat.size * b + 31) // 32 + 3, np.uint64)
     vals = flat - np.uint64(lo)
     for j in range(b):
         bit = (vals >> np.uint64(j)) & np.uint64(1)

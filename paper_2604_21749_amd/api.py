@@ -188,7 +188,8 @@ class GpuMesh:
 class CompressedGeometry:
     """Device buffers and parameters of a compressed mesh (curast_compressed, Sec. 4.6)."""
     packed: torch.Tensor                    # int32 [words] bits of the packed index stream (cuda)
-    qpos: torch.Tensor                      # int16 [V, 3] bits of the uint16 positions (cuda)
+    qpos: torch.Tensor                      # int16 [3 V + 1] bits of the uint16 positions, then one
+                                            # padding element (cuda)
     index_min: int
     index_bits: int
     lo: np.ndarray                          # float32 [3]
@@ -213,7 +214,9 @@ def _mesh_struct(m: GpuMesh, keep: list, check: bool = True) -> MeshStruct:
     if m.compressed is not None:
         if check:
             _check_cuda(m.compressed.packed, torch.int32, "packed indices")
-            _check_cuda(m.compressed.qpos, torch.int16, "quantized positions", 3)
+            _check_cuda(m.compressed.qpos, torch.int16, "quantized positions")
+            if m.compressed.qpos.numel() != 3 * m.compressed.num_vertices + 1:
+                raise ValueError("quantized positions must hold 3 V + 1 elements")
         cs = m.compressed.struct()
         keep.append(cs)
         s.compressed = C.addressof(cs)
@@ -377,10 +380,9 @@ class Context:
         stream = _stream(mesh.device)
         self._check(lib().curast_compress_prepare(self._h, C.byref(ms), C.byref(info), C.byref(words), stream))
         packed = torch.empty(int(words.value), dtype=torch.int32, device=mesh.device)
-        qpos = torch.empty((mesh.num_vertices, 3), dtype=torch.int16, device=mesh.device)
+        qpos = torch.empty(3 * mesh.num_vertices + 1, dtype=torch.int16, device=mesh.device)
         self._check(lib().curast_compress(self._h, C.byref(ms), C.byref(info),
-                                          packed.data_ptr() if packed.numel() else None,
-                                          qpos.data_ptr() if qpos.numel() else None, stream))
+                                          packed.data_ptr(), qpos.data_ptr(), stream))
         geo = CompressedGeometry(packed, qpos, int(info.index_min), int(info.index_bits),
                                  np.array(info.lo[:], np.float32), np.array(info.step[:], np.float32),
                                  mesh.num_vertices, mesh.num_triangles)

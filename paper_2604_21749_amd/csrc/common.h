@@ -47,7 +47,7 @@ struct ViewDesc {                 // 48 B
 struct MeshDesc {                 // 80 B
     const float* pos;             // [V][3], or NULL when compressed
     const uint32_t* idx;          // [T][3], or the packed index stream when compressed
-    const uint16_t* qpos;         // [V][3] quantized positions when compressed, else NULL
+    const uint16_t* qpos;         // [3 V + 1] quantized positions (+1 padding) when compressed, else NULL
     uint64_t T;
     uint32_t V;
     uint32_t idx_bits;            // 0: plain indices; else bits per packed index
@@ -144,7 +144,8 @@ struct RasterArgs {
     uint32_t* tile_count;         // [n_tiles] parts per tile (zeroed by the clear kernel)
     uint32_t* tile_offset;        // [n_tiles + 1] exclusive prefix of tile_count
     uint32_t* q3_binned;          // [q3_cap] large-record index of every part, grouped by tile
-    uint32_t compressed_parts;    // bit p: stage-1 part p has a compressed mesh (host-side choice)
+    uint32_t compressed_parts;    // bit p: stage-1 part p has a compressed mesh; bit p + 8: every
+                                  // mesh of part p is compressed (host-side kernel choice)
 };
 
 struct ResolveArgs {

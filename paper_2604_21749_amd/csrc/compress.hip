@@ -94,13 +94,18 @@ __global__ void __launch_bounds__(256) pack_kernel(const uint32_t* __restrict__ 
     gl(out)[w] = word;
 }
 
-// One lane per position component: q = clamp(rint((p - lo) * scale), 0, 65535) in binary32.
+// One lane per position component: q = clamp(rint((p - lo) * scale), 0, 65535) in binary32;
+// element n, the padding, is 0.
 __global__ void __launch_bounds__(256) quantize_kernel(const float* __restrict__ pos, uint64_t n, float lx, float ly,
                                                        float lz, float sx, float sy, float sz,
                                                        uint16_t* __restrict__ out)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i > n) return;
+    if (i == n) {
+        gl(out)[i] = 0;
+        return;
+    }
     const uint32_t c = (uint32_t)(i % 3);
     const float lo = c == 0 ? lx : c == 1 ? ly : lz;
     const float sc = c == 0 ? sx : c == 1 ? sy : sz;
@@ -128,8 +133,7 @@ hipError_t launch_compress(const uint32_t* idx, uint64_t n_idx, uint32_t bits, u
 {
     if (words) pack_kernel<<<blocks_of(words, 0xFFFFFFFFu), 256, 0, s>>>(idx, n_idx, bits, base, packed, words);
     const uint64_t n = 3ull * V;
-    if (n)
-        quantize_kernel<<<blocks_of(n, 0xFFFFFFFFu), 256, 0, s>>>(pos, n, lo[0], lo[1], lo[2], scale[0], scale[1],
+    quantize_kernel<<<blocks_of(n + 1, 0xFFFFFFFFu), 256, 0, s>>>(pos, n, lo[0], lo[1], lo[2], scale[0], scale[1],
                                                                   scale[2], qpos);
     return hipGetLastError();
 }

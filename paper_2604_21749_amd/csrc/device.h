@@ -35,17 +35,45 @@ struct Clip {                 // clip-space vertex: x, y and the positive view d
 
 // ----------------------------------------------------------------------------------------------
 // Mesh geometry access, plain or compressed (Sec. 4.6).  Packed index i occupies bits
-// [i b, (i + 1) b) of a little-endian stream of 32-bit words; it is read with one 64-bit load of
-// the two words around it (the stream carries one word of padding).  A quantized position
-// component decodes as fmaf(q, step, lo).
+// [i b, (i + 1) b) of a little-endian stream of 32-bit words.  The 3 b bits of a triangle are
+// read with one load of the 2 words (b <= 11) or 4 words (b > 11) from the word holding its first
+// bit; the stream carries three words of padding so that this stays inside it.  The 6 bytes of a
+// quantized vertex are read with one 8-byte load from the 4-byte boundary at or below them (the
+// positions carry one padding element); a component decodes as fmaf(q, step, lo).
 // ----------------------------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t packed_index(const MeshDesc& M, uint64_t i)
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+typedef uint32_t u32x4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+
+// Bits [s, s + 32) of the 128-bit little-endian value w0..w3, for s < 96.
+__device__ __forceinline__ uint32_t window_bits(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t w3, uint32_t s)
 {
-    const uint64_t bit = i * (uint64_t)M.idx_bits;
+    const uint32_t j = s >> 5;
+    const uint32_t lo = j == 0 ? w0 : j == 1 ? w1 : w2;
+    const uint32_t hi = j == 0 ? w1 : j == 1 ? w2 : w3;
+    return __builtin_amdgcn_alignbit(hi, lo, s & 31);
+}
+
+__device__ __forceinline__ void packed_triangle(const MeshDesc& M, uint64_t t, uint32_t (&v)[3])
+{
+    const uint32_t b = M.idx_bits;
+    const uint64_t bit = 3 * t * (uint64_t)b;
     const CURAST_GLOBAL uint32_t* w = gl(M.idx) + (bit >> 5);
-    const uint64_t pair = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
-    const uint32_t mask = M.idx_bits >= 32 ? 0xFFFFFFFFu : ((1u << M.idx_bits) - 1u);
-    return M.idx_min + ((uint32_t)(pair >> (bit & 31)) & mask);
+    const uint32_t o = (uint32_t)bit & 31;
+    uint32_t w0, w1, w2 = 0, w3 = 0;
+    if (b <= 11) {                            // o + 3 b <= 64: two words
+        const u32x2_a4 d = *(const CURAST_GLOBAL u32x2_a4*)w;
+        w0 = d.x;
+        w1 = d.y;
+    } else {                                  // o + 3 b <= 127: four words
+        const u32x4_a4 d = *(const CURAST_GLOBAL u32x4_a4*)w;
+        w0 = d.x;
+        w1 = d.y;
+        w2 = d.z;
+        w3 = d.w;
+    }
+    const uint32_t mask = b >= 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) v[k] = M.idx_min + (window_bits(w0, w1, w2, w3, o + k * b) & mask);
 }
 
 // Vertex indices of triangle t (CMP: the mesh is known to be compressed; otherwise decided per
@@ -55,8 +83,7 @@ __device__ __forceinline__ void mesh_triangle(const MeshDesc& M, uint64_t t, uin
 {
     const bool packed = CMP < 0 ? M.idx_bits != 0 : CMP != 0;
     if (packed) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k) v[k] = packed_index(M, 3 * t + k);
+        packed_triangle(M, t, v);
     } else {
         const CURAST_GLOBAL uint32_t* ip = gl(M.idx) + 3 * t;
         v[0] = ip[0];
@@ -70,9 +97,12 @@ __device__ __forceinline__ void mesh_vertex(const MeshDesc& M, uint32_t v, float
 {
     const bool packed = CMP < 0 ? M.qpos != nullptr : CMP != 0;
     if (packed) {
-        const CURAST_GLOBAL uint16_t* q = gl(M.qpos) + 3 * (size_t)v;
+        const uint64_t e = 3 * (uint64_t)v;   // first element; the load starts at element e & ~1
+        const u32x2_a4 d = *(const CURAST_GLOBAL u32x2_a4*)((const CURAST_GLOBAL uint32_t*)gl(M.qpos) + (e >> 1));
+        const uint64_t q = ((uint64_t)d.x | ((uint64_t)d.y << 32)) >> ((e & 1) * 16);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) p[c] = __builtin_fmaf((float)q[c], M.step[c], M.lo[c]);
+        for (int c = 0; c < 3; ++c)
+            p[c] = __builtin_fmaf((float)(uint32_t)((q >> (16 * c)) & 0xFFFFu), M.step[c], M.lo[c]);
     } else {
         const CURAST_GLOBAL float* q = gl(M.pos) + 3 * (size_t)v;
         p[0] = q[0];

@@ -1303,12 +1303,16 @@ hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool
     }
 }
 
-// Launches whose meshes are all plain use the kernel without the per-mesh compression branch.
+// Launches whose meshes are all plain or all compressed use a kernel without the per-mesh
+// compression branch (Sec. 4.6 notes the same for its kernels); mixed launches decide per mesh.
 template <int BLOCK, int TPT, bool STRIPS>
 static hipError_t stage1_fast_dispatch(const RasterArgs& a, bool stats, uint32_t grid, hipStream_t s)
 {
-    const bool cmp = (a.compressed_parts >> a.part) & 1u;
-    if (cmp) {
+    const bool any = (a.compressed_parts >> a.part) & 1u, all = (a.compressed_parts >> (a.part + 8)) & 1u;
+    if (all) {
+        if (stats) stage1_fast_kernel<BLOCK, TPT, STRIPS, true, 1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+        else stage1_fast_kernel<BLOCK, TPT, STRIPS, false, 1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    } else if (any) {
         if (stats) stage1_fast_kernel<BLOCK, TPT, STRIPS, true, -1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
         else stage1_fast_kernel<BLOCK, TPT, STRIPS, false, -1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
     } else {

@@ -68,7 +68,7 @@ struct Staging {
 };
 
 struct GraphEntry {
-    uint64_t key[8];
+    uint64_t key[9];
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -439,7 +439,8 @@ struct Plan {
     uint64_t total_pixels = 0;
     uint64_t max_batches = 0;        // without any culling (graph grid bound)
     uint64_t pair_count = 0;
-    bool compressed = false;         // some mesh is compressed (stage 1 then decodes per mesh)
+    bool compressed = false;         // some mesh is compressed
+    uint32_t compressed_parts = 0;   // RasterArgs::compressed_parts of this frame's stage-1 parts
     size_t max_draws = 0;            // without any culling
     size_t off_views = 0, off_meshes = 0, off_segs = 0, off_draws = 0, bytes = 0, max_bytes = 0;
 };
@@ -534,9 +535,12 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
     // loaded triangle over many draws), then the rest; mode 3 sends every mesh to the first
     auto shared_mesh = [&](uint32_t m) { return o.s1_mode == 3 || mesh_draw_count[m] >= 2; };
     for (int pass = 0; pass < 2; ++pass) {
+        bool any_cmp = false, all_cmp = true;
         for (uint32_t m = 0; m < M; ++m) {
             const uint32_t dc = mesh_draw_count[m];
             if (!dc || !meshes[m].num_triangles || shared_mesh(m) != (pass == 0)) continue;
+            any_cmp |= meshes[m].compressed != nullptr;
+            all_cmp &= meshes[m].compressed != nullptr;
             Segment sg{};
             sg.batch_begin = P.hdr.total_batches;
             sg.mesh = m;
@@ -549,6 +553,8 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
             P.tri_draws += meshes[m].num_triangles * (uint64_t)dc;
         }
         if (pass == 0) P.hdr.shared_batches = P.hdr.total_batches;
+        const uint32_t part = pass + 1;
+        if (any_cmp) P.compressed_parts |= (1u << part) | (all_cmp ? 1u << (part + 8) : 0u);
     }
     P.hdr.n_segs = (uint32_t)P.segs.size();
     P.hdr.n_views = n_views;
@@ -599,7 +605,7 @@ RasterArgs make_args(curast_ctx* ctx, const Plan& P)
     a.tile_count = ctx->tile_count;
     a.tile_offset = ctx->tile_offset;
     a.q3_binned = ctx->q3_binned;
-    a.compressed_parts = P.compressed ? 0x6u : 0u;
+    a.compressed_parts = P.compressed_parts;
     return a;
 }
 
@@ -696,12 +702,13 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
     // graph path: one captured sequence per structure (sizes of the descriptor block, grid bound,
     // options); replays copy the new descriptor contents from the same pinned buffer
     const uint32_t grid1 = grid_for(P.max_batches);
-    uint64_t key[8] = {(uint64_t)M, (uint64_t)n_views, (uint64_t)P.max_bytes, (uint64_t)grid1,
+    uint64_t key[9] = {(uint64_t)M, (uint64_t)n_views, (uint64_t)P.max_bytes, (uint64_t)grid1,
                        ((uint64_t)ctx->opt.s1_block << 32) | (ctx->opt.s1_tris_per_thread << 8) |
                            (ctx->opt.s1_multi_tris_per_thread << 4) | ctx->opt.s1_mode,
                        ((uint64_t)ctx->opt.s2_waves << 32) | ctx->opt.s3_blocks,
-                       ((uint64_t)ctx->opt.flags << 32) | ((uint64_t)P.compressed << 31) | ctx->opt.small_px,
-                       ((uint64_t)ctx->opt.medium_px << 32) | ctx->opt.s1_draws_per_item};
+                       ((uint64_t)ctx->opt.flags << 32) | ctx->opt.small_px,
+                       ((uint64_t)ctx->opt.medium_px << 32) | ctx->opt.s1_draws_per_item,
+                       ((uint64_t)P.compressed << 32) | P.compressed_parts};
     GraphEntry* ge = nullptr;
     for (auto& g : ctx->graphs)
         if (std::memcmp(g.key, key, sizeof key) == 0) ge = &g;
@@ -1085,7 +1092,7 @@ int curast_compress_prepare(curast_ctx* ctx, const curast_mesh* mesh, curast_com
         info->lo[c] = lo;
         info->step[c] = (float)(((double)hi - (double)lo) / 65535.0);
     }
-    *index_words = (n_idx * info->index_bits + 31) / 32 + 1;
+    *index_words = (n_idx * info->index_bits + 31) / 32 + 3;
     return CURAST_OK;
 }
 
@@ -1093,14 +1100,14 @@ int curast_compress(curast_ctx* ctx, const curast_mesh* mesh, const curast_compr
                     uint16_t* positions, void* stream)
 {
     if (!ctx) return CURAST_E_INVALID;
-    if (!info || (mesh && !packed_indices) || (mesh && mesh->num_vertices && !positions))
+    if (!info || !packed_indices || !positions)
         return fail(ctx, CURAST_E_INVALID, "NULL pointer argument");
     int rc = check_plain_mesh(ctx, mesh);
     if (rc) return rc;
     if (info->index_bits < 1 || info->index_bits > 32) return fail(ctx, CURAST_E_INVALID, "index_bits must lie in [1, 32]");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     const uint64_t n_idx = 3ull * mesh->num_triangles;
-    const uint64_t words = (n_idx * info->index_bits + 31) / 32 + 1;
+    const uint64_t words = (n_idx * info->index_bits + 31) / 32 + 3;
     const float scale[3] = {quant_scale(info->step[0]), quant_scale(info->step[1]), quant_scale(info->step[2])};
     HIP_TRY(ctx, launch_compress(mesh->indices, n_idx, info->index_bits, info->index_min, packed_indices, words,
                                  mesh->vertices, mesh->num_vertices, info->lo, scale, positions,

@@ -63,7 +63,9 @@ def test_compression_matches_the_oracle_bit_for_bit(ctx):
         assert (c.index_min, c.index_bits) == (lo_i, bits)
         assert np.array_equal(c.lo, lo) and np.array_equal(c.step, step)
         assert np.array_equal(c.packed.cpu().numpy().view(np.uint32), words)
-        assert np.array_equal(c.qpos.cpu().numpy().view(np.uint16), q)
+        qp = c.qpos.cpu().numpy().view(np.uint16)
+        assert qp.shape == (3 * len(m.pos) + 1,) and qp[-1] == 0
+        assert np.array_equal(qp[:-1].reshape(-1, 3), q)
         assert np.array_equal(decompressed(m).idx, m.idx)
 
 

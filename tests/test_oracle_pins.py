@@ -467,7 +467,7 @@ def test_index_width_matches_the_paper_example_and_boundaries():
     assert O.index_bits(g["index_max"] - g["index_min"]) == g["bits"]
     idx = np.array([[2500, 2750, 3000], [2999, 2501, 2600]], np.uint32)
     lo, bits, words = O.compress_indices(idx)
-    assert (lo, bits) == (2500, 9) and words.size == (6 * 9 + 31) // 32 + 1
+    assert (lo, bits) == (2500, 9) and words.size == (6 * 9 + 31) // 32 + 3
     # widths at powers of two: span 2^k - 1 needs k bits, span 2^k needs k + 1
     for k in range(1, 32):
         assert O.index_bits((1 << k) - 1) == k and O.index_bits(1 << k) == k + 1
@@ -489,7 +489,7 @@ def test_index_packing_round_trip_and_layout():
         for i in (0, 1, 7, 122):
             w, r = divmod(i * b, 32)
             assert (int(words[w]) >> r) & 1 == int(flat[i]) & 1
-        assert words[-1] == 0 or words.size == 1
+        assert words.size == (123 * b + 31) // 32 + 3 and np.all(words[-3:] == 0)
 
 
 def test_position_quantization_bounds():
