@@ -271,6 +271,57 @@ int curast_resolve_supersampled(curast_ctx* ctx, const curast_mesh* meshes, uint
                                 void* stream);
 
 /*
+ * A mip-mapped RGBA8 texture for curast_resolve_textured.  Texel (i, j) of level l holds R in
+ * bits 0-7, G in 8-15, B in 16-23, A in 24-31, decoded as byte * (1.0f / 255.0f).  Level l is
+ * max(1, width >> l) x max(1, height >> l) texels, row-major, row j at texture coordinate
+ * v = (j + 0.5) / height_l; the levels follow each other without gaps, level 0 first, so
+ * `texels` holds sum over l of width_l * height_l words (curast_texture_texels).
+ */
+typedef struct {
+    const uint32_t* texels;     /* device */
+    uint32_t width, height;     /* level 0: powers of two in [1, 16384] */
+    uint32_t levels;            /* 1 .. 1 + log2(max(width, height)) */
+} curast_texture;
+
+/* Texels of a texture with all its levels (0 for an invalid size or level count). */
+uint64_t curast_texture_texels(uint32_t width, uint32_t height, uint32_t levels);
+
+/*
+ * Fill levels 1 .. levels - 1 of a texture from level 0: texel (i, j) of level l + 1 is the
+ * per-channel mean of texels (2i, 2j), (2i + 1, 2j), (2i, 2j + 1), (2i + 1, 2j + 1) of level l,
+ * with coordinates clamped to level l and the sum rounded as (a + b + c + d + 2) >> 2.  Level 0 is
+ * not touched.  texels: device, curast_texture_texels(width, height, levels) words.
+ */
+int curast_build_mips(curast_ctx* ctx, uint32_t* texels, uint32_t width, uint32_t height, uint32_t levels,
+                      void* stream);
+
+/*
+ * Textured resolve with world-space mip-level selection (Sec. 4.4, "Shading and Mip Mapping").
+ * For a covered pixel (px, py) of the view, the rays through the window points
+ * (px + 0.5, py + 0.5), (px + 1.5, py + 0.5), (px + 0.5, py + 1.5) and (px + 1.5, py + 1.5)
+ * (the pixel and its right, top and top-right neighbours; row 0 is at the bottom) are intersected
+ * with the plane of the pixel's triangle, and the UVs of the intersections are interpolated or
+ * extrapolated from its vertices.  Barycentrics of a ray-plane hit do not change under the
+ * affine map from world to clip space, so they are solved there, which needs no division by w
+ * and holds for vertices behind the camera: with n = ((sx - W/2) / (W/2), (sy - H/2) / (H/2)),
+ *   a_k = fmaf(-n.x, w_k, x_k),  c_k = fmaf(-n.y, w_k, y_k)      (clip x, y, w of vertex k)
+ *   e = a x c  (e0 = a1 c2 - a2 c1, ...),  s = (e0 + e1) + e2
+ *   u = ((e0 u0 + e1 u1) + e2 u2) / s,  v likewise.
+ * The level of detail is lod = log2(max((u_max - u_min) width, (v_max - v_min) height)) over the
+ * four hits, clamped to [0, levels - 1]; levels - 1 when a hit is not finite.  The colour is the
+ * trilinear sample at the first hit: bilinear within a level (texel centres at (i + 0.5) / w_l,
+ * wrap-around addressing, weights from x = frac(u) w_l - 0.5), blended between levels
+ * floor(lod) and floor(lod) + 1 by lod - floor(lod).  Every step is binary32 with the operation
+ * order above.
+ *   uvs: host array of M device pointers, mesh m's per-vertex texture coordinates [V_m][2];
+ *   textures: host array of M textures (meshes may share one);
+ *   out: device [height][width][4] float RGBA; empty pixels and pixels whose centre hit is not
+ *   finite get 0.
+ */
+int curast_resolve_textured(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* view,
+                            const float* const* uvs, const curast_texture* textures, float* out, void* stream);
+
+/*
  * Resolve one mesh from explicit screen positions (the differentiable form):
  *   visbuffer device [H][W]; indices device [T][3]; pos_ss device [V][3] (sx, sy, w);
  *   attrs device [V][C]; out device [H][W][C].  Pixels whose ID is outside

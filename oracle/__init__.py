@@ -36,6 +36,12 @@ def lib():
         P = C.c_void_p
         _lib.orc_num_pairs.restype = C.c_int64
         _lib.orc_num_pairs.argtypes = [P, C.c_uint32]
+        _lib.orc_texture_texels.restype = C.c_uint64
+        _lib.orc_texture_texels.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32]
+        _lib.orc_sample_trilinear.restype = None
+        _lib.orc_sample_trilinear.argtypes = [P, C.c_float, C.c_float, C.c_float, P]
+        _lib.orc_texture_lod.restype = C.c_float
+        _lib.orc_texture_lod.argtypes = [P, P, P, C.c_int]
         for name, args in {
             "orc_id_bases": [P, C.c_uint32, P],
             "orc_decode_id": [P, C.c_uint32, P, C.c_int64, P, P, P],
@@ -48,6 +54,8 @@ def lib():
             "orc_quantize_positions": [P, C.c_uint32, P, P, P],
             "orc_decode_positions": [P, C.c_uint32, P, P, P],
             "orc_resolve": [P, C.c_uint32, P, P, P, C.c_uint32, P, C.c_int],
+            "orc_build_mips": [P, C.c_uint32, C.c_uint32, C.c_uint32],
+            "orc_resolve_textured": [P, C.c_uint32, P, P, P, P, P, C.c_int],
             "orc_resolve_screen": [P, C.c_int32, C.c_int32, P, C.c_uint64, C.c_int64, P, C.c_uint32, P, C.c_uint32, P],
             "orc_resolve_screen_f64": [P, C.c_int32, C.c_int32, P, C.c_uint64, C.c_int64, P, C.c_uint32, P, C.c_uint32, P],
             "orc_resolve_screen_backward_f64": [P, C.c_int32, C.c_int32, P, C.c_uint64, C.c_int64, P, C.c_uint32, P,
@@ -260,6 +268,74 @@ def box_filter(samples: np.ndarray, k: int) -> np.ndarray:
 def resolve_supersampled(meshes, view_hi, vis_hi: np.ndarray, attrs, k: int, threads: int = 0) -> np.ndarray:
     """Resolve every sample of the k-times-larger view, then box-filter k x k blocks."""
     return box_filter(resolve(meshes, view_hi, vis_hi, attrs, threads=threads), k)
+
+
+# ----------------------------------------------------------------------------------------------
+# textured resolve (Sec. 4.4, "Shading and Mip Mapping")
+# ----------------------------------------------------------------------------------------------
+class _Tex(C.Structure):
+    _fields_ = [("texels", C.c_void_p), ("width", C.c_uint32), ("height", C.c_uint32), ("levels", C.c_uint32)]
+
+
+def texture_texels(width: int, height: int, levels: int) -> int:
+    """Words of an RGBA8 mip chain (0 for invalid sizes / level counts)."""
+    return int(lib().orc_texture_texels(width, height, levels))
+
+
+def level_shape(width: int, height: int, level: int):
+    return max(1, height >> level), max(1, width >> level)
+
+
+def build_mips(level0: np.ndarray, levels: int) -> np.ndarray:
+    """The whole chain (uint32 words, levels concatenated) from level 0 [height, width] uint32."""
+    h, w = level0.shape
+    n = texture_texels(w, h, levels)
+    if not n:
+        raise ValueError("invalid texture size or level count")
+    chain = np.zeros(n, np.uint32)
+    chain[:w * h] = np.ascontiguousarray(level0, np.uint32).reshape(-1)
+    _check(lib().orc_build_mips(chain.ctypes.data, w, h, levels), "build_mips")
+    return chain
+
+
+def texture_level(chain: np.ndarray, width: int, height: int, level: int) -> np.ndarray:
+    off = sum(level_shape(width, height, j)[0] * level_shape(width, height, j)[1] for j in range(level))
+    hl, wl = level_shape(width, height, level)
+    return chain[off:off + hl * wl].reshape(hl, wl)
+
+
+def _tex_struct(chain, width, height, levels):
+    return _Tex(chain.ctypes.data, width, height, levels)
+
+
+def sample_trilinear(chain: np.ndarray, width: int, height: int, levels: int, u: float, v: float, lod: float):
+    chain = np.ascontiguousarray(chain, np.uint32)
+    t = _tex_struct(chain, width, height, levels)
+    out = np.zeros(4, np.float32)
+    lib().orc_sample_trilinear(C.byref(t), float(u), float(v), float(lod), out.ctypes.data)
+    return out
+
+
+def texture_lod(width: int, height: int, levels: int, u, v, finite: bool = True) -> float:
+    u = np.ascontiguousarray(u, np.float32)
+    v = np.ascontiguousarray(v, np.float32)
+    dummy = np.zeros(1, np.uint32)
+    t = _tex_struct(dummy, width, height, levels)
+    return float(lib().orc_texture_lod(C.byref(t), u.ctypes.data, v.ctypes.data, int(finite)))
+
+
+def resolve_textured(meshes, view, vis: np.ndarray, uvs, textures, threads: int = 0) -> np.ndarray:
+    """RGBA [H, W, 4]; uvs[m] float32 [V, 2]; textures[m] = (chain uint32, width, height, levels)."""
+    pk = _Pack(meshes, view)
+    keep_uv = [np.ascontiguousarray(a, np.float32) for a in uvs]
+    keep_tx = [np.ascontiguousarray(t[0], np.uint32) for t in textures]
+    uptr = (C.c_void_p * max(1, len(keep_uv)))(*[a.ctypes.data for a in keep_uv])
+    tarr = (_Tex * max(1, len(textures)))(*[_tex_struct(c, t[1], t[2], t[3]) for c, t in zip(keep_tx, textures)])
+    vis = np.ascontiguousarray(vis, np.uint64)
+    out = np.empty((view.height, view.width, 4), np.float32)
+    _check(lib().orc_resolve_textured(pk.meshes, pk.M, C.byref(pk.view), vis.ctypes.data, uptr, tarr,
+                                      out.ctypes.data, threads), "resolve_textured")
+    return out
 
 
 def resolve_screen(vis, idx, id_base, pos_ss, attrs) -> np.ndarray:

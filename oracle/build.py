@@ -8,7 +8,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["raster.c", "brute.c", "resolve.c", "compress.c"]
+SOURCES = ["raster.c", "brute.c", "resolve.c", "compress.c", "texture.c"]
 LIB = os.path.join(HERE, "liboracle.so")
 
 

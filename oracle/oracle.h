@@ -98,12 +98,31 @@ int orc_coverage_counts(const orc_mesh* meshes, uint32_t M, const orc_view* view
 /* Independent brute-force transcription: every pixel against every triangle, no bounding box. */
 int orc_rasterize_brute(const orc_mesh* meshes, uint32_t M, const orc_view* view, uint64_t* vis);
 
-/* Unsnapped screen positions (sx, sy, w) of every vertex of one mesh instance: [V][3]. */
 /* Compressed geometry (Sec. 4.6): binary32 quantization of positions to 16 bits relative to lo with
  * scale (float)(1 / (double)step) (0 for step 0), and the decoding fmaf(q, step, lo). */
 int orc_quantize_positions(const float* pos, uint32_t V, const float lo[3], const float step[3], uint16_t* out);
 int orc_decode_positions(const uint16_t* q, uint32_t V, const float lo[3], const float step[3], float* out);
 
+/* Textures (Sec. 4.4, "Shading and Mip Mapping"): RGBA8 mip chains, level l is
+ * max(1, width >> l) x max(1, height >> l) texels, levels concatenated from level 0. */
+typedef struct {
+    const uint32_t* texels;
+    uint32_t width, height, levels;
+} orc_texture;
+
+/* Words of a chain (0 if the sizes are not powers of two in [1, 16384] or levels is out of
+ * range); the 2x2 box-filtered chain (rounded mean, coordinates clamped) from level 0; one
+ * trilinear wrap-around sample; the level of detail of four UV hits (see texture.c). */
+uint64_t orc_texture_texels(uint32_t width, uint32_t height, uint32_t levels);
+int orc_build_mips(uint32_t* texels, uint32_t width, uint32_t height, uint32_t levels);
+void orc_sample_trilinear(const orc_texture* tex, float u, float v, float lod, float out[4]);
+float orc_texture_lod(const orc_texture* tex, const float u[4], const float v[4], int finite);
+
+/* Textured resolve: out [H][W][4] RGBA; uvs[m] is mesh m's [V][2], textures[m] its texture. */
+int orc_resolve_textured(const orc_mesh* meshes, uint32_t M, const orc_view* view, const uint64_t* vis,
+                         const float* const* uvs, const orc_texture* textures, float* out, int nthreads);
+
+/* Unsnapped screen positions (sx, sy, w) of every vertex of one mesh instance: [V][3]. */
 int orc_project(const orc_mesh* mesh, uint32_t instance, const orc_view* view, float* pos_ss);
 
 /* fp32 resolve of a visibility buffer: out [H][W][C]; attrs[m] is mesh m's [V][C]. */

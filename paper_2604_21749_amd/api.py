@@ -60,6 +60,10 @@ class MeshStruct(C.Structure):
                 ("bsphere", C.c_float * 4), ("compressed", C.c_void_p)]
 
 
+class TextureStruct(C.Structure):
+    _fields_ = [("texels", C.c_void_p), ("width", C.c_uint32), ("height", C.c_uint32), ("levels", C.c_uint32)]
+
+
 class ViewStruct(C.Structure):
     _fields_ = [("view_proj", C.c_float * 16), ("near_plane", C.c_float), ("width", C.c_int32),
                 ("height", C.c_int32), ("visbuffer", C.c_void_p)]
@@ -88,6 +92,9 @@ SIGNATURES = {
     "curast_compress_prepare": (C.c_int, [_P, _P, _P, _P, _P]),
     "curast_compress": (C.c_int, [_P, _P, _P, _P, _P, _P]),
     "curast_resolve_supersampled": (C.c_int, [_P, _P, C.c_uint32, _P, C.c_uint32, _P, C.c_uint32, _P, _P]),
+    "curast_texture_texels": (C.c_uint64, [C.c_uint32, C.c_uint32, C.c_uint32]),
+    "curast_build_mips": (C.c_int, [_P, _P, C.c_uint32, C.c_uint32, C.c_uint32, _P]),
+    "curast_resolve_textured": (C.c_int, [_P, _P, C.c_uint32, _P, _P, _P, _P, _P]),
     "curast_resolve_screen": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, C.c_uint64, C.c_uint64, _P, C.c_uint32,
                                         _P, C.c_uint32, _P, _P]),
     "curast_resolve_backward": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, C.c_uint64, C.c_uint64, _P,
@@ -182,6 +189,24 @@ class GpuMesh:
         inst = None if m.inst is None else np.ascontiguousarray(m.inst, np.float32)
         bs = None if m.bsphere is None else np.ascontiguousarray(m.bsphere, np.float32)
         return GpuMesh(pos, idx, inst, bs, attrs)
+
+
+def texture_texels(width: int, height: int, levels: int) -> int:
+    """curast_texture_texels: words of an RGBA8 mip chain (0 for invalid sizes or level counts)."""
+    return int(lib().curast_texture_texels(width, height, levels))
+
+
+@dataclass
+class Texture:
+    """A mip-mapped RGBA8 texture in device memory (curast_texture): `texels` holds every level,
+    level 0 first, as int32 bits of the RGBA8 words."""
+    texels: torch.Tensor                    # int32 [curast_texture_texels(width, height, levels)] (cuda)
+    width: int
+    height: int
+    levels: int
+
+    def struct(self) -> TextureStruct:
+        return TextureStruct(self.texels.data_ptr(), self.width, self.height, self.levels)
 
 
 @dataclass
@@ -419,6 +444,62 @@ class Context:
             rc = lib().curast_resolve_supersampled(self._h, arr, len(meshes), C.byref(vs), ss, ptrs, Cn,
                                                    out.data_ptr(), _stream(vis.device))
         self._check(rc)
+        return out
+
+    def texture(self, level0: torch.Tensor, levels: Optional[int] = None) -> Texture:
+        """A texture from its level 0 (int32 [height, width] RGBA8 words, cuda) with the full chain
+        (or `levels` levels) filled by curast_build_mips."""
+        _check_cuda(level0, torch.int32, "level 0")
+        if level0.dim() != 2:
+            raise ValueError("level 0 must be [height, width]")
+        h, w = int(level0.shape[0]), int(level0.shape[1])
+        if levels is None:
+            levels = max(w, h).bit_length()
+        n = texture_texels(w, h, levels)
+        if not n:
+            raise ValueError("texture sizes must be powers of two in [1, 16384] with 1 .. 1 + log2(max) levels")
+        texels = torch.empty(n, dtype=torch.int32, device=level0.device)
+        texels[:w * h].copy_(level0.reshape(-1))
+        self.build_mips(texels, w, h, levels)
+        return Texture(texels, w, h, levels)
+
+    def build_mips(self, texels: torch.Tensor, width: int, height: int, levels: int):
+        """curast_build_mips: fills levels 1 .. levels - 1 of `texels` from its level 0."""
+        _check_cuda(texels, torch.int32, "texels")
+        if texels.numel() < texture_texels(width, height, levels):
+            raise ValueError("texels is smaller than the mip chain")
+        self._check(lib().curast_build_mips(self._h, texels.data_ptr(), width, height, levels,
+                                            _stream(texels.device)))
+
+    def resolve_textured(self, meshes: Sequence[GpuMesh], view, vis: torch.Tensor, uvs: Sequence[torch.Tensor],
+                         textures: Sequence[Texture], out: Optional[torch.Tensor] = None):
+        """curast_resolve_textured: RGBA float32 [H, W, 4], trilinear texture samples with the mip
+        level from four ray-plane hits per pixel (Sec. 4.4)."""
+        if not (len(meshes) == len(uvs) == len(textures)):
+            raise ValueError("one UV array and one texture per mesh")
+        keep = []
+        arr = (MeshStruct * max(1, len(meshes)))(*[_mesh_struct(m, keep) for m in meshes])
+        for m, uv in zip(meshes, uvs):
+            _check_cuda(uv, torch.float32, "uvs", 2)
+            if uv.shape[0] != m.num_vertices:
+                raise ValueError("uvs[m] must have one row per vertex of mesh m")
+        for t in textures:
+            _check_cuda(t.texels, torch.int32, "texels")
+            if not texture_texels(t.width, t.height, t.levels):
+                raise ValueError("texture sizes must be powers of two in [1, 16384] with 1 .. 1 + log2(max) levels")
+            if t.texels.numel() < texture_texels(t.width, t.height, t.levels):
+                raise ValueError("texture texels smaller than its mip chain")
+        ptrs = (C.c_void_p * max(1, len(uvs)))(*[u.data_ptr() for u in uvs])
+        tex = (TextureStruct * max(1, len(textures)))(*[t.struct() for t in textures])
+        shape = (view.height, view.width, 4)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=vis.device)
+        _check_cuda(out, torch.float32, "out")
+        if tuple(out.shape) != shape:
+            raise ValueError(f"out must have shape {list(shape)}")
+        vs = _view_struct(view.vp, view.near, view.width, view.height, vis)
+        self._check(lib().curast_resolve_textured(self._h, arr, len(meshes), C.byref(vs), ptrs, tex, out.data_ptr(),
+                                                  _stream(vis.device)))
         return out
 
     def resolve_screen(self, vis: torch.Tensor, indices: torch.Tensor, pos_ss: torch.Tensor, attrs: torch.Tensor,

@@ -148,6 +148,13 @@ struct RasterArgs {
                                   // mesh of part p is compressed (host-side kernel choice)
 };
 
+// A mip-mapped RGBA8 texture: level l is max(1, w >> l) x max(1, h >> l) texels from off[l].
+struct TexDesc {
+    const uint32_t* texels;
+    uint32_t w, h, levels, pad;
+    uint32_t off[16];
+};
+
 struct ResolveArgs {
     const unsigned long long* vis;
     int32_t W, H;
@@ -160,6 +167,7 @@ struct ResolveArgs {
     uint32_t C;
     float* out;                   // [H][W][C], or [H/ss][W/ss][C] when supersampled
     uint32_t ss;                  // samples per axis and output pixel (1: no supersampling)
+    const TexDesc* tex;           // [M] textures of the textured resolve (attrs are then the UVs)
 };
 
 struct ScreenArgs {

@@ -88,9 +88,11 @@ struct PixelHit {
     float b[3];
 };
 
-__device__ __forceinline__ bool resolve_hit(const ResolveArgs& a, const uint64_t* B, const DrawDesc* __restrict__ pairs,
-                                            const MeshDesc* __restrict__ meshes, const float* const* __restrict__ attrs,
-                                            uint64_t p, PixelHit& h)
+// The (mesh, instance) pair and vertex indices of the triangle stored at pixel p; false for an
+// empty pixel or an invalid triangle.
+__device__ __forceinline__ bool pixel_triangle(const ResolveArgs& a, const uint64_t* B, const DrawDesc* __restrict__ pairs,
+                                               const MeshDesc* __restrict__ meshes, uint64_t p, uint32_t& pair,
+                                               uint32_t (&vi)[3])
 {
     const uint32_t np = a.n_pairs;
     const unsigned long long key = gl(a.vis)[p];
@@ -102,12 +104,20 @@ __device__ __forceinline__ bool resolve_hit(const ResolveArgs& a, const uint64_t
         if (B[mid] <= id) lo = mid;
         else hi = mid;
     }
+    const MeshDesc& M = meshes[pairs[lo].mesh];
+    mesh_triangle(M, id - B[lo], vi);
+    pair = lo;
+    return vi[0] < M.V && vi[1] < M.V && vi[2] < M.V;
+}
+
+__device__ __forceinline__ bool resolve_hit(const ResolveArgs& a, const uint64_t* B, const DrawDesc* __restrict__ pairs,
+                                            const MeshDesc* __restrict__ meshes, const float* const* __restrict__ attrs,
+                                            uint64_t p, PixelHit& h)
+{
+    uint32_t lo, vi[3];
+    if (!pixel_triangle(a, B, pairs, meshes, p, lo, vi)) return false;
     const DrawDesc& D = pairs[lo];
     const MeshDesc& M = meshes[D.mesh];
-    const uint64_t t = id - B[lo];
-    uint32_t vi[3];
-    mesh_triangle(M, t, vi);
-    if (vi[0] >= M.V || vi[1] >= M.V || vi[2] >= M.V) return false;
     float sx[3], sy[3], w[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -196,6 +206,151 @@ __global__ void __launch_bounds__(256) resolve_ss_kernel(ResolveArgs a, const ui
 #pragma unroll
     for (uint32_t c = 0; c < kMaxChannels; ++c)
         if (c < a.C) o[c] = acc[c] * scale;
+}
+
+// ----------------------------------------------------------------------------------------------
+// Textured resolve (Sec. 4.4, "Shading and Mip Mapping").  Rays through the pixel and its right,
+// top and top-right neighbours hit the triangle's plane; their barycentrics are solved in clip
+// space (the world-to-clip map is affine, so they equal the world-space ones, and no vertex is
+// divided by its w):
+//   n = ((sx - W/2) / (W/2), (sy - H/2) / (H/2)),  a_k = fmaf(-n.x, w_k, x_k),  c_k likewise,
+//   e = a x c,  s = (e0 + e1) + e2,  uv = ((e0 uv0 + e1 uv1) + e2 uv2) / s.
+// lod = log2 of the larger UV extent of the four hits in texels, clamped to the chain; the colour
+// is the trilinear, wrap-around sample at the pixel's own hit.
+// ----------------------------------------------------------------------------------------------
+__device__ __forceinline__ float4 bilinear(const TexDesc& T, uint32_t l, float u, float v)
+{
+    const uint32_t wl = max(1u, T.w >> l), hl = max(1u, T.h >> l);
+    const CURAST_GLOBAL uint32_t* L = gl(T.texels) + T.off[l];
+    const float fu = u - floorf(u), fv = v - floorf(v);
+    const float x = fu * (float)wl - 0.5f, y = fv * (float)hl - 0.5f;
+    const float x0 = floorf(x), y0 = floorf(y);
+    const float ax = x - x0, ay = y - y0;
+    // x0 lies in [-1, wl - 1] and y0 in [-1, hl - 1]; the clamps only guard the addressing
+    const int32_t ix = (int32_t)x0, iy = (int32_t)y0;
+    const uint32_t i0 = min(ix < 0 ? wl - 1 : (uint32_t)ix, wl - 1), i1 = ix + 1 >= (int32_t)wl ? 0u : (uint32_t)(ix + 1);
+    const uint32_t j0 = min(iy < 0 ? hl - 1 : (uint32_t)iy, hl - 1), j1 = iy + 1 >= (int32_t)hl ? 0u : (uint32_t)(iy + 1);
+    const uint32_t t00 = L[(size_t)j0 * wl + i0], t10 = L[(size_t)j0 * wl + min(i1, wl - 1)];
+    const uint32_t t01 = L[(size_t)min(j1, hl - 1) * wl + i0], t11 = L[(size_t)min(j1, hl - 1) * wl + min(i1, wl - 1)];
+    const float k = 1.0f / 255.0f;
+    float r[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const float c00 = (float)((t00 >> (8 * c)) & 0xFFu) * k, c10 = (float)((t10 >> (8 * c)) & 0xFFu) * k;
+        const float c01 = (float)((t01 >> (8 * c)) & 0xFFu) * k, c11 = (float)((t11 >> (8 * c)) & 0xFFu) * k;
+        const float r0 = c00 + ax * (c10 - c00);
+        const float r1 = c01 + ax * (c11 - c01);
+        r[c] = r0 + ay * (r1 - r0);
+    }
+    return make_float4(r[0], r[1], r[2], r[3]);
+}
+
+__global__ void __launch_bounds__(256) resolve_textured_kernel(ResolveArgs a, const uint64_t* __restrict__ bases,
+                                                               const DrawDesc* __restrict__ pairs,
+                                                               const MeshDesc* __restrict__ meshes,
+                                                               const float* const* __restrict__ uvs,
+                                                               const TexDesc* __restrict__ texs)
+{
+    __shared__ uint64_t s_bases[kLdsBases + 1];
+    const uint64_t* B = stage_bases(a, bases, s_bases);
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (uint64_t)a.W * (uint64_t)a.H) return;
+    CURAST_GLOBAL float4* o = (CURAST_GLOBAL float4*)gl(a.out) + p;
+    uint32_t pr, vi[3];
+    if (!pixel_triangle(a, B, pairs, meshes, p, pr, vi)) {
+        *o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        return;
+    }
+    const DrawDesc& D = pairs[pr];
+    const MeshDesc& M = meshes[D.mesh];
+    float cx[3], cy[3], cw[3], tu[3], tv[3];
+    const CURAST_GLOBAL float* uv = gl(uvs[D.mesh]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float q[3];
+        mesh_vertex(M, vi[k], q);
+        const Clip c = transform(D.A, q[0], q[1], q[2]);
+        cx[k] = c.x;
+        cy[k] = c.y;
+        cw[k] = c.w;
+        tu[k] = uv[2 * (size_t)vi[k]];
+        tv[k] = uv[2 * (size_t)vi[k] + 1];
+    }
+    const int32_t px = (int32_t)(p % (uint64_t)a.W), py = (int32_t)(p / (uint64_t)a.W);
+    float su[4], sv[4];
+    bool finite = true;
+#pragma unroll
+    for (int smp = 0; smp < 4; ++smp) {
+        const float sx = (float)px + ((smp & 1) ? 1.5f : 0.5f), sy = (float)py + ((smp & 2) ? 1.5f : 0.5f);
+        const float nx = (sx - a.hW) / a.hW, ny = (sy - a.hH) / a.hH;
+        float e_a[3], e_c[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            e_a[k] = __builtin_fmaf(-nx, cw[k], cx[k]);
+            e_c[k] = __builtin_fmaf(-ny, cw[k], cy[k]);
+        }
+        const float e0 = e_a[1] * e_c[2] - e_a[2] * e_c[1];
+        const float e1 = e_a[2] * e_c[0] - e_a[0] * e_c[2];
+        const float e2 = e_a[0] * e_c[1] - e_a[1] * e_c[0];
+        const float s = (e0 + e1) + e2;
+        su[smp] = ((e0 * tu[0] + e1 * tu[1]) + e2 * tu[2]) / s;
+        sv[smp] = ((e0 * tv[0] + e1 * tv[1]) + e2 * tv[2]) / s;
+        finite = finite && __builtin_isfinite(su[smp]) && __builtin_isfinite(sv[smp]);
+    }
+    if (!__builtin_isfinite(su[0]) || !__builtin_isfinite(sv[0])) {
+        *o = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        return;
+    }
+    const TexDesc& T = texs[D.mesh];
+    const float top = (float)(T.levels - 1);
+    float lod = top;
+    if (finite) {
+        float umin = su[0], umax = su[0], vmin = sv[0], vmax = sv[0];
+#pragma unroll
+        for (int smp = 1; smp < 4; ++smp) {
+            umin = fminf(umin, su[smp]);
+            umax = fmaxf(umax, su[smp]);
+            vmin = fminf(vmin, sv[smp]);
+            vmax = fmaxf(vmax, sv[smp]);
+        }
+        const float du = (umax - umin) * (float)T.w, dv = (vmax - vmin) * (float)T.h;
+        lod = log2f(fmaxf(du, dv));
+        lod = lod > 0.0f ? lod : 0.0f;
+        lod = lod > top ? top : lod;
+    }
+    const uint32_t l0 = (uint32_t)floorf(lod);
+    const float t = lod - (float)l0;
+    float4 c = bilinear(T, l0, su[0], sv[0]);
+    if (t > 0.0f && l0 + 1 < T.levels) {
+        const float4 c1 = bilinear(T, l0 + 1, su[0], sv[0]);
+        c.x = c.x + t * (c1.x - c.x);
+        c.y = c.y + t * (c1.y - c.y);
+        c.z = c.z + t * (c1.z - c.z);
+        c.w = c.w + t * (c1.w - c.w);
+    }
+    *o = c;
+}
+
+// Level l + 1 of a chain from level l: per-channel rounded mean of a 2 x 2 block, coordinates
+// clamped to level l.
+__global__ void __launch_bounds__(256) mip_kernel(const uint32_t* __restrict__ src, uint32_t pw, uint32_t ph,
+                                                  uint32_t* __restrict__ dst, uint32_t cw, uint32_t ch)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (uint64_t)cw * ch) return;
+    const uint32_t x = (uint32_t)(i % cw), y = (uint32_t)(i / cw);
+    const uint32_t x0 = 2 * x, y0 = 2 * y, x1 = min(2 * x + 1, pw - 1), y1 = min(2 * y + 1, ph - 1);
+    const CURAST_GLOBAL uint32_t* S = gl(src);
+    const uint32_t q0 = S[(size_t)y0 * pw + x0], q1 = S[(size_t)y0 * pw + x1];
+    const uint32_t q2 = S[(size_t)y1 * pw + x0], q3 = S[(size_t)y1 * pw + x1];
+    uint32_t out = 0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const uint32_t sum = 2 + ((q0 >> (8 * c)) & 0xFFu) + ((q1 >> (8 * c)) & 0xFFu) + ((q2 >> (8 * c)) & 0xFFu) +
+                             ((q3 >> (8 * c)) & 0xFFu);
+        out |= (sum >> 2) << (8 * c);
+    }
+    gl(dst)[i] = out;
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -316,6 +471,26 @@ hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s)
     } else {
         resolve_kernel<<<blocks_for((uint64_t)a.W * (uint64_t)a.H), 256, 0, s>>>(a, a.bases, a.pairs, a.meshes,
                                                                                  a.attrs);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve_textured(const ResolveArgs& a, hipStream_t s)
+{
+    resolve_textured_kernel<<<blocks_for((uint64_t)a.W * (uint64_t)a.H), 256, 0, s>>>(a, a.bases, a.pairs, a.meshes,
+                                                                                      a.attrs, a.tex);
+    return hipGetLastError();
+}
+
+// Levels 1 .. levels - 1 from level 0, one launch per level (each reads the previous one).
+hipError_t launch_build_mips(uint32_t* texels, uint32_t w, uint32_t h, uint32_t levels, hipStream_t s)
+{
+    uint64_t off = 0;
+    for (uint32_t l = 0; l + 1 < levels; ++l) {
+        const uint32_t pw = max(1u, w >> l), ph = max(1u, h >> l), cw = max(1u, w >> (l + 1)), ch = max(1u, h >> (l + 1));
+        uint32_t* src = texels + off;
+        off += (uint64_t)pw * ph;
+        mip_kernel<<<blocks_for((uint64_t)cw * ch), 256, 0, s>>>(src, pw, ph, texels + off, cw, ch);
     }
     return hipGetLastError();
 }

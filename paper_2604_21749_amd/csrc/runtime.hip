@@ -38,6 +38,8 @@ hipError_t launch_compress(const uint32_t* idx, uint64_t n_idx, uint32_t bits, u
                            uint64_t words, const float* pos, uint32_t V, const float lo[3], const float scale[3],
                            uint16_t* qpos, hipStream_t s);
 hipError_t launch_resolve(const ResolveArgs& a, hipStream_t s);
+hipError_t launch_resolve_textured(const ResolveArgs& a, hipStream_t s);
+hipError_t launch_build_mips(uint32_t* texels, uint32_t w, uint32_t h, uint32_t levels, hipStream_t s);
 hipError_t launch_resolve_screen(const ScreenArgs& a, hipStream_t s);
 hipError_t launch_resolve_backward(const ScreenArgs& a, hipStream_t s);
 }  // namespace curast
@@ -774,7 +776,7 @@ void collect_timings(curast_ctx* ctx)
 }
 
 int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view& view,
-                       const float* const* attrs, ResolveArgs& a, size_t& bytes_out)
+                       const float* const* attrs, const curast_texture* textures, ResolveArgs& a, size_t& bytes_out)
 {
     uint64_t np = 0;
     for (uint32_t m = 0; m < M; ++m) np += n_inst(meshes[m]);
@@ -783,7 +785,8 @@ int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, c
     const size_t off_pairs = align_up(sizeof(uint64_t) * (np + 1), 256);
     const size_t off_meshes = align_up(off_pairs + sizeof(DrawDesc) * std::max<uint64_t>(np, 1), 256);
     const size_t off_attrs = align_up(off_meshes + sizeof(MeshDesc) * std::max<uint32_t>(M, 1), 256);
-    const size_t bytes = align_up(off_attrs + sizeof(float*) * std::max<uint32_t>(M, 1), 256);
+    const size_t off_tex = align_up(off_attrs + sizeof(float*) * std::max<uint32_t>(M, 1), 256);
+    const size_t bytes = textures ? align_up(off_tex + sizeof(TexDesc) * std::max<uint32_t>(M, 1), 256) : off_tex;
     int rc = ensure_staging(ctx, ctx->resolve_stage, bytes);
     if (rc) return rc;
     char* h = static_cast<char*>(ctx->resolve_stage.host);
@@ -791,10 +794,24 @@ int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, c
     DrawDesc* pairs = reinterpret_cast<DrawDesc*>(h + off_pairs);
     MeshDesc* md = reinterpret_cast<MeshDesc*>(h + off_meshes);
     const float** ap = reinterpret_cast<const float**>(h + off_attrs);
+    TexDesc* td = reinterpret_cast<TexDesc*>(h + off_tex);
     uint64_t base = 0, p = 0;
     for (uint32_t m = 0; m < M; ++m) {
         md[m] = mesh_desc(meshes[m]);
         ap[m] = attrs[m];
+        if (textures) {
+            TexDesc t{};
+            t.texels = textures[m].texels;
+            t.w = textures[m].width;
+            t.h = textures[m].height;
+            t.levels = textures[m].levels;
+            uint32_t off = 0;
+            for (uint32_t l = 0; l < t.levels; ++l) {
+                t.off[l] = off;
+                off += std::max(1u, t.w >> l) * std::max(1u, t.h >> l);
+            }
+            td[m] = t;
+        }
         for (uint32_t i = 0; i < n_inst(meshes[m]); ++i, ++p) {
             bases[p] = base;
             draw_matrix(view.view_proj, meshes[m].instances ? meshes[m].instances + 12ull * i : nullptr, pairs[p].A);
@@ -815,6 +832,7 @@ int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, c
     a.pairs = reinterpret_cast<const DrawDesc*>(d + off_pairs);
     a.meshes = reinterpret_cast<const MeshDesc*>(d + off_meshes);
     a.attrs = reinterpret_cast<const float* const*>(d + off_attrs);
+    a.tex = textures ? reinterpret_cast<const TexDesc*>(d + off_tex) : nullptr;
     a.n_pairs = (uint32_t)np;
     bytes_out = bytes;
     return CURAST_OK;
@@ -1009,7 +1027,7 @@ int resolve_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const c
     hipStream_t s = static_cast<hipStream_t>(stream);
     ResolveArgs a{};
     size_t bytes = 0;
-    rc = build_resolve_desc(ctx, meshes, M, *view, attrs, a, bytes);
+    rc = build_resolve_desc(ctx, meshes, M, *view, attrs, nullptr, a, bytes);
     if (rc) return rc;
     a.C = C;
     a.out = out;
@@ -1039,6 +1057,70 @@ int curast_resolve_supersampled(curast_ctx* ctx, const curast_mesh* meshes, uint
                                 void* stream)
 {
     return resolve_impl(ctx, meshes, M, view, attrs, C, out, samples_per_axis, stream);
+}
+
+uint64_t curast_texture_texels(uint32_t width, uint32_t height, uint32_t levels)
+{
+    auto pow2 = [](uint32_t d) { return d && !(d & (d - 1)) && d <= (uint32_t)kMaxDim; };
+    if (!pow2(width) || !pow2(height) || levels < 1) return 0;
+    const uint32_t max_levels = 1 + (31 - (uint32_t)__builtin_clz(std::max(width, height)));
+    if (levels > max_levels) return 0;
+    uint64_t n = 0;
+    for (uint32_t l = 0; l < levels; ++l) n += (uint64_t)std::max(1u, width >> l) * std::max(1u, height >> l);
+    return n;
+}
+
+int curast_build_mips(curast_ctx* ctx, uint32_t* texels, uint32_t width, uint32_t height, uint32_t levels,
+                      void* stream)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    if (!texels) return fail(ctx, CURAST_E_INVALID, "NULL pointer argument");
+    if (!curast_texture_texels(width, height, levels))
+        return fail(ctx, CURAST_E_INVALID, "texture sizes must be powers of two in [1, 16384] with 1 .. 1 + log2(max) levels");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, launch_build_mips(texels, width, height, levels, static_cast<hipStream_t>(stream)));
+    return CURAST_OK;
+}
+
+int curast_resolve_textured(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* view,
+                            const float* const* uvs, const curast_texture* textures, float* out, void* stream)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    if (!view || !out || (M && (!meshes || !uvs || !textures))) return fail(ctx, CURAST_E_INVALID, "NULL pointer argument");
+    int rc = check_view(ctx, *view);
+    if (rc) return rc;
+    uint64_t total = 0;
+    for (uint32_t m = 0; m < M; ++m) {
+        rc = check_mesh(ctx, meshes[m]);
+        if (rc) return rc;
+        const curast_texture& t = textures[m];
+        if (!curast_texture_texels(t.width, t.height, t.levels))
+            return fail(ctx, CURAST_E_INVALID, "texture sizes must be powers of two in [1, 16384] with 1 .. 1 + log2(max) levels");
+        if (meshes[m].num_triangles && (!uvs[m] || !t.texels))
+            return fail(ctx, CURAST_E_INVALID, "uvs[m] and textures[m].texels must be set for a mesh with triangles");
+        total += meshes[m].num_triangles * (uint64_t)n_inst(meshes[m]);
+        if (total > kMaxIds) return fail(ctx, CURAST_E_ID_RANGE, "more than 2^36 triangle instances");
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ResolveArgs a{};
+    size_t bytes = 0;
+    rc = build_resolve_desc(ctx, meshes, M, *view, uvs, textures, a, bytes);
+    if (rc) return rc;
+    a.C = 2;
+    a.out = out;
+    a.ss = 1;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->resolve_stage.dev, ctx->resolve_stage.host, bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->resolve_stage.ev, s));
+    ctx->resolve_stage.pending = true;
+    TimedFrame* tf = begin_timing(ctx);
+    if (tf) hipEventRecord(tf->ev[7], s);
+    HIP_TRY(ctx, launch_resolve_textured(a, s));
+    if (tf) {
+        hipEventRecord(tf->ev[8], s);
+        tf->used[kTResolve] = 1;
+    }
+    return CURAST_OK;
 }
 
 namespace {

@@ -363,6 +363,34 @@ def _hf_camera(width, height) -> View:
     return orbit_camera((0.5, 0.0, 0.5), math.radians(45.0), math.radians(45.0), 1.2, width, height)
 
 
+# ----------------------------------------------------------------------------------------------
+# Textures and texture coordinates for the textured resolve (Sec. 4.4).  The paper's scenes carry
+# photographic textures; these are seeded procedural stand-ins with the same role: RGBA8, power of
+# two, with detail at every scale so that mip levels differ.
+# ----------------------------------------------------------------------------------------------
+def texture_rgba8(width: int, height: int, seed: int, lines: int = 32) -> np.ndarray:
+    """uint32 [height, width] RGBA8 (R in the low byte): fBm value noise through a colour ramp,
+    darkened on grid lines every `lines` texels, alpha 255."""
+    n = max(width, height, 2)
+    f = fbm2_grid(n, seed, octaves=6)[:height, :width]
+    f = np.clip(0.5 + 0.6 * f, 0.0, 1.0)
+    r = f
+    g = 0.5 + 0.5 * np.sin(6.0 * f)
+    b = 1.0 - f
+    jj, ii = np.meshgrid(np.arange(height), np.arange(width), indexing="ij")
+    dark = ((ii % lines) == 0) | ((jj % lines) == 0)
+    shade = np.where(dark, 0.3, 1.0)
+    to8 = lambda c: np.clip(np.rint(c * shade * 255.0), 0, 255).astype(np.uint32)
+    return to8(r) | (to8(g) << 8) | (to8(b) << 16) | (np.uint32(255) << 24)
+
+
+def planar_uv(pos: np.ndarray, axes=(0, 2), scale=1.0, offset=0.0) -> np.ndarray:
+    """float32 [V, 2] texture coordinates (pos[:, axes[0]], pos[:, axes[1]]) * scale + offset."""
+    p = np.asarray(pos, np.float64)
+    uv = np.stack([p[:, axes[0]], p[:, axes[1]]], axis=1) * scale + offset
+    return uv.astype(np.float32)
+
+
 def scene_c1() -> Scene:
     """Plain pipeline at oracle size: jittered UV sphere 256 x 512 (r = 1, per-vertex
     N(0, 1e-3) jitter, seed 1) plus a 20 x 20 ground quad at y = -1 that crosses the near plane;

@@ -59,6 +59,7 @@ int main(void) {
   O(curast_mesh, compressed);
   P(curast_compressed); O(curast_compressed, index_min); O(curast_compressed, lo); O(curast_compressed, step);
   P(curast_view); O(curast_view, near_plane); O(curast_view, visbuffer);
+  P(curast_texture); O(curast_texture, width); O(curast_texture, levels);
   P(curast_stats); O(curast_stats, atomics);
   return 0;
 }
@@ -85,6 +86,9 @@ int main(void) {
     assert got["curast_view"] == C.sizeof(api.ViewStruct)
     assert got["curast_view.near_plane"] == api.ViewStruct.near_plane.offset
     assert got["curast_view.visbuffer"] == api.ViewStruct.visbuffer.offset
+    assert got["curast_texture"] == C.sizeof(api.TextureStruct)
+    assert got["curast_texture.width"] == api.TextureStruct.width.offset
+    assert got["curast_texture.levels"] == api.TextureStruct.levels.offset
     assert got["curast_stats"] == C.sizeof(api.StatsStruct)
     assert got["curast_stats.atomics"] == api.StatsStruct.atomics.offset
 
@@ -111,12 +115,26 @@ def test_null_context_is_rejected_without_a_gpu(api):
     assert L.curast_resolve_supersampled(None, None, 0, None, 2, None, 3, None, None) == api.E_INVALID
     assert L.curast_compress_prepare(None, None, None, None, None) == api.E_INVALID
     assert L.curast_compress(None, None, None, None, None, None) == api.E_INVALID
+    assert L.curast_build_mips(None, None, 8, 8, 4, None) == api.E_INVALID
+    assert L.curast_resolve_textured(None, None, 0, None, None, None, None, None) == api.E_INVALID
     assert L.curast_resolve_screen(None, None, 8, 8, None, 0, 0, None, 1, None, 3, None, None) == api.E_INVALID
     assert L.curast_resolve_backward(None, None, 8, 8, None, 0, 0, None, 1, None, 3, None, None, None,
                                      None) == api.E_INVALID
     assert L.curast_autotune(None, None, 0, None, 0, None, None, None) == api.E_INVALID
     assert L.curast_get_stats(None, None) == api.E_INVALID
     assert L.curast_set_options(None, None) == api.E_INVALID
+
+
+def test_texture_chain_sizes_match_the_oracle(api):
+    """curast_texture_texels (host only) against the oracle's chain sizes, including invalid sizes
+    and level counts (0)."""
+    import oracle as O
+    for w in (1, 2, 3, 8, 64, 100, 1024, 16384, 32768):
+        for h in (1, 4, 6, 256, 16384):
+            for levels in (0, 1, 2, 5, 11, 15, 16):
+                assert api.texture_texels(w, h, levels) == O.texture_texels(w, h, levels), (w, h, levels)
+    assert api.texture_texels(16384, 16384, 15) == sum((16384 >> l) ** 2 for l in range(15))
+    assert api.texture_texels(4, 1, 3) == 4 + 2 + 1 and api.texture_texels(4, 1, 4) == 0
 
 
 def _cpu_mesh(api, m):

@@ -13,6 +13,11 @@ index, a transposed operand, a wrong tie rule, an off-by-one bound) fails at lea
   * clip path vs an fp64 analytic coverage of the visible part
   * resolve vs the paper's world-space ray/plane formulation (Sec. 4.4) and constant attributes
   * backward: partition of unity, linearity in the attributes, fp64 analytic vs central FD
+  * supersampling: identity at k = 1, covered fractions, symmetric sample grid
+  * compressed geometry: the paper's 9-bit example, bit layout, quantization bounds
+  * textured resolve: mip chain by hand, bilinear ramps and wrap, trilinear blend, the level of
+    detail in closed form, and the uv / level of detail of a near-plane-crossing ground plane
+    against fp64 world-space ray casting (Sec. 4.4)
 """
 import json
 import math
@@ -562,3 +567,143 @@ def test_backward_position_gradient_matches_central_fd():
     lp = np.sum(np.where(cov[..., None], O.resolve_screen_f64(vis, m.idx, 0, pss + dp, m.attrs) - target, 0) ** 2)
     lm = np.sum(np.where(cov[..., None], O.resolve_screen_f64(vis, m.idx, 0, pss - dp, m.attrs) - target, 0) ** 2)
     assert np.isclose((lp - lm) / 2, np.sum(gp * dp), rtol=1e-5)
+
+
+# ----------------------------------------------------------------------------------------------
+# textured resolve (Sec. 4.4, "Shading and Mip Mapping")
+# ----------------------------------------------------------------------------------------------
+def _level_constant_chain(w, h, L, step=20):
+    """A chain whose level l is the constant step * l in every channel."""
+    chain = np.zeros(O.texture_texels(w, h, L), np.uint32)
+    off = 0
+    for l in range(L):
+        hl, wl = O.level_shape(w, h, l)
+        chain[off:off + hl * wl] = np.uint32(step * l * 0x01010101)
+        off += hl * wl
+    return chain
+
+
+def test_mip_chain_pins():
+    assert O.texture_texels(8, 16, 5) == 8 * 16 + 4 * 8 + 2 * 4 + 1 * 2 + 1 * 1
+    assert O.texture_texels(8, 8, 4) == 85 and O.texture_texels(8, 8, 5) == 0 and O.texture_texels(6, 4, 1) == 0
+    # a constant stays constant at every level
+    ch = O.build_mips(np.full((16, 8), 0x80402010, np.uint32), 5)
+    assert np.all(ch == 0x80402010)
+    # one-texel checkerboard of 0 and 255: every coarser texel is (0 + 255 + 0 + 255 + 2) >> 2 = 128
+    cb = np.where((np.add.outer(np.arange(8), np.arange(8)) & 1) == 1, 0xFFFFFFFF, 0).astype(np.uint32)
+    ch = O.build_mips(cb, 4)
+    assert np.all(ch[64:] == 0x80808080)
+    # by hand, a 4 x 1 row (rows clamped): [0, 1, 2, 5] -> [(0+1+0+1+2)>>2, (2+5+2+5+2)>>2] = [1, 4] -> [3]
+    ch = O.build_mips(np.array([[0, 1, 2, 5]], np.uint32), 3)
+    assert ch.tolist() == [0, 1, 2, 5, 1, 4, 3]
+    assert O.texture_level(ch, 4, 1, 1).tolist() == [[1, 4]]
+
+
+def test_trilinear_sampling_pins():
+    # 256 x 4 ramp (R = column), one level: between texel centres 255 R = frac(u) 256 - 0.5
+    w, h = 256, 4
+    ch = O.build_mips(np.tile(np.arange(w, dtype=np.uint32), (h, 1)), 1)
+    for u in (0.01, 0.25, 0.5, 0.777, 0.99, 3.25, -0.75):
+        x = (u - math.floor(u)) * 256 - 0.5
+        assert 0 <= x <= 255
+        assert abs(O.sample_trilinear(ch, w, h, 1, u, 0.3, 0.0)[0] * 255 - x) < 1e-3, u
+    # wrap-around: at u = 0 the sample lies halfway between the last texel (255) and the first (0)
+    assert abs(O.sample_trilinear(ch, w, h, 1, 0.0, 0.3, 0.0)[0] * 255 - 127.5) < 1e-3
+    # the same along v with a row ramp (G = row) on a 4 x 256 texture
+    ch = O.build_mips(np.tile((np.arange(256, dtype=np.uint32) << 8)[:, None], (1, 4)), 1)
+    for v in (0.1, 0.5, 0.9):
+        assert abs(O.sample_trilinear(ch, 4, 256, 1, 0.2, v, 0.0)[1] * 255 - (v * 256 - 0.5)) < 1e-3
+    # between levels: linear in lod, clamped to [0, levels - 1]
+    w = h = 64
+    chain = _level_constant_chain(w, h, 7)
+    for lod, expect in ((-3.0, 0.0), (0.0, 0.0), (0.25, 5.0), (2.5, 50.0), (5.75, 115.0), (6.0, 120.0), (40.0, 120.0)):
+        assert np.allclose(O.sample_trilinear(chain, w, h, 7, 0.37, 0.61, lod) * 255, expect, atol=2e-3), lod
+
+
+def test_texture_lod_pins():
+    w, h, L = 256, 128, 9
+    for s, t, expect in ((1.0, 0.5, 0.0), (4.0, 1.0, 2.0), (3.0, 5.0, math.log2(5.0)), (0.25, 0.25, 0.0),
+                         (1e6, 0.0, 8.0)):
+        u = [0.25, 0.25 + s / w, 0.25, 0.25 + s / w]
+        v = [0.5, 0.5, 0.5 + t / h, 0.5 + t / h]
+        assert abs(O.texture_lod(w, h, L, u, v) - expect) < 1e-4, (s, t)
+    assert O.texture_lod(w, h, L, [0.3] * 4, [0.3] * 4) == 0.0
+    assert O.texture_lod(w, h, L, [0.3] * 4, [0.3] * 4, finite=False) == 8.0
+    # the extent of all four hits, not the step from the first: a rotated footprint spans 4 texels
+    u = [0.5, 0.5 + 2 / w, 0.5 - 2 / w, 0.5]
+    v = [0.5, 0.5 + 2 / h, 0.5 + 2 / h, 0.5 + 4 / h]
+    assert abs(O.texture_lod(w, h, L, u, v) - 2.0) < 1e-4
+
+
+def test_textured_resolve_lod_closed_form():
+    """A fronto-parallel quad filling the view with u = k_u x + 1/2, v = k_v y + 1/2: adjacent pixels
+    are 1/16 world units apart at depth 2 (fovy 90, 64 px), so the footprint is s = 16 k_u 256 / 256
+    texels and the level of detail clamp(log2 s, 0, 8)."""
+    Wd = Hd = 64
+    view = _view_cam(Wd, Hd, fovy=90.0)
+    quad = np.array([[-3, -3, -2], [3, -3, -2], [3, 3, -2], [-3, 3, -2]], np.float32)
+    qidx = np.array([[0, 1, 2], [0, 2, 3]], np.uint32)
+    mesh = W.Mesh(quad, qidx)
+    vis = O.rasterize([mesh], view)
+    assert np.all(vis != O.EMPTY)
+    chain = _level_constant_chain(256, 256, 9)
+    for s in (0.5, 1.0, 2.0, 3.3, 16.0, 1000.0):
+        ku = s / 16.0
+        uv = np.stack([quad[:, 0] * ku + 0.5, quad[:, 1] * (ku / 2) + 0.5], axis=1).astype(np.float32)
+        out = O.resolve_textured([mesh], view, vis, [uv], [(chain, 256, 256, 9)])
+        expect = 20.0 * min(max(math.log2(s), 0.0), 8.0)
+        assert np.max(np.abs(out[..., 0] * 255 - expect)) < 5e-3, s
+        assert np.array_equal(out[..., 0], out[..., 1]) and np.all(out[..., 3] == out[..., 0])
+
+
+def _ground_rays_f64(view, px, py, dx=0.5, dy=0.5):
+    """fp64 world-space ray through window point (px + dx, py + dy) of the C1 camera (eye (0, 0, 3),
+    looking down -z, fovy 60, aspect 1) hitting the ground plane y = -1: (x, z) of the hit."""
+    f = 1.0 / math.tan(math.radians(W.FOVY_DEG) / 2.0)
+    nx = 2.0 * (px + dx) / view.width - 1.0
+    ny = 2.0 * (py + dy) / view.height - 1.0
+    d = np.stack([nx / f, ny / f, -np.ones_like(nx)], axis=-1)
+    t = -1.0 / d[..., 1]
+    return t * d[..., 0], 3.0 + t * d[..., 2]
+
+
+def test_textured_resolve_near_plane_ground_vs_world_space_rays():
+    """The C1 ground quad reaches behind the camera (its triangles cross the near plane).  With
+    u = (x + 10) / 20, v = (z + 10) / 20, the oracle's uv at each pixel (read back through R and G
+    ramps) and its level of detail (through a level-constant chain) equal fp64 ray casting in
+    world space: the pixel's ray and the rays through its right, top and top-right neighbours
+    intersected with the plane y = -1."""
+    s = W.scene_c1()
+    ground = s.meshes[1]
+    view = s.views[0]
+    vis = O.rasterize([ground], view)
+    cov = vis != O.EMPTY
+    assert cov.sum() > 50000
+    uv = np.stack([(ground.pos[:, 0] + 10) / 20, (ground.pos[:, 2] + 10) / 20], axis=1).astype(np.float32)
+    py, px = np.nonzero(cov)
+    # uv: R ramps with the column, G with the row (one level)
+    ramp = (np.arange(256, dtype=np.uint32)[None, :] | (np.arange(256, dtype=np.uint32)[:, None] << 8))
+    out = O.resolve_textured([ground], view, vis, [uv], [(O.build_mips(ramp, 1), 256, 256, 1)])
+    x, z = _ground_rays_f64(view, px, py)
+    u_ref, v_ref = (x + 10) / 20, (z + 10) / 20
+    xr, xg = out[py, px, 0] * 255.0, out[py, px, 1] * 255.0
+    inner = (u_ref * 256 - 0.5 > 0.01) & (u_ref * 256 - 0.5 < 254.99) & (v_ref * 256 - 0.5 > 0.01) & \
+            (v_ref * 256 - 0.5 < 254.99)
+    assert inner.sum() > 0.9 * len(px)
+    assert np.max(np.abs((xr + 0.5) / 256 - u_ref)[inner]) < 2e-5
+    assert np.max(np.abs((xg + 0.5) / 256 - v_ref)[inner]) < 2e-5
+    # level of detail: extent of the four hits' uv (now 8 (x + 10) / 20, 8 (z + 10) / 20, so the
+    # plane spans several levels) in texels of a 256 x 256 chain of 9 levels
+    out = O.resolve_textured([ground], view, vis, [uv * np.float32(8)],
+                             [(_level_constant_chain(256, 256, 9), 256, 256, 9)])
+    us, vs = [], []
+    for dx, dy in ((0.5, 0.5), (1.5, 0.5), (0.5, 1.5), (1.5, 1.5)):
+        x, z = _ground_rays_f64(view, px, py, dx, dy)
+        us.append(8 * (x + 10) / 20)
+        vs.append(8 * (z + 10) / 20)
+    us, vs = np.array(us), np.array(vs)
+    rho = np.maximum((us.max(0) - us.min(0)) * 256, (vs.max(0) - vs.min(0)) * 256)
+    lod_ref = np.clip(np.log2(rho), 0, 8)
+    lod = out[py, px, 0] * 255.0 / 20.0
+    assert lod_ref.max() > 4.0 and lod_ref.min() < 2.0
+    assert np.max(np.abs(lod - lod_ref)) < 2e-3
