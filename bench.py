@@ -106,8 +106,9 @@ def run_headline(args, api, torch, W):
     multi, single = split_meshes(api, scene, gm)
     ss = {} if args.no_secondary else run_supersampling(args, api, torch, ctx, gm, attrs, view, ms)
     cmp = {} if args.no_secondary else run_compressed(args, api, torch, ctx, gm, attrs, view, vis_count)
+    tex = {} if args.no_secondary else run_textured(args, api, torch, W, ctx, gm, attrs, view, vis)
     return {"scene": scene, "gm": gm, "ctx": ctx, "vis": vis, "ms": ms, "stage_ms": stage_ms, "supersampling": ss,
-            "compressed": cmp,
+            "compressed": cmp, "textured": tex,
             "visible": vis_count, "stats": st, "multi": multi, "single": single, "options": ctx.options()}
 
 
@@ -174,6 +175,39 @@ def run_compressed(args, api, torch, ctx, gm, attrs, view, visible):
                                            / HBM_PEAK_GBS, 4)}
     log(f"[bench] compressed {res}")
     del cm, vis, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_textured(args, api, torch, W, ctx, gm, attrs, view, vis):
+    """Resolve of the headline frame's visibility buffer with textures (Sec. 4.4): per-pixel UVs
+    interpolated at four ray-plane hits, mip level from their extent, trilinear RGBA8 sample.
+    Height field: u, v = 64 x, 64 z over a 4096^2 texture; spheres: 4 x + 1/2, 4 y + 1/2 over
+    1024^2.  Compared with the per-vertex RGB resolve of the same buffer."""
+    t0 = time.perf_counter()
+    uvs = [(g.pos[:, [0, 2]] * 64.0).contiguous() if g.num_instances == 1 else (g.pos[:, [0, 1]] * 4.0 + 0.5).contiguous()
+           for g in gm]
+    sizes = [4096 if g.num_instances == 1 else 1024 for g in gm]
+    texs = [ctx.texture(torch.from_numpy(W.texture_rgba8(n, n, 80 + i).view(np.int32)).cuda())
+            for i, n in enumerate(sizes)]
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    out4 = torch.empty((view.height, view.width, 4), dtype=torch.float32, device="cuda")
+    out3 = torch.empty((view.height, view.width, 3), dtype=torch.float32, device="cuda")
+    res = {"textures": [f"{n}x{n} RGBA8, {t.levels} levels" for n, t in zip(sizes, texs)],
+           "setup_s": round(setup_s, 2)}
+    reps = max(4, args.steps)
+    for name, fn in (("textured_ms", lambda: ctx.resolve_textured(gm, view, vis, uvs, texs, out=out4)),
+                     ("rgb_ms", lambda: ctx.resolve(gm, view, vis, attrs, out=out3))):
+        fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        res[name] = round((time.perf_counter() - t1) * 1000.0 / reps, 4)
+    log(f"[bench] textured resolve {res}")
+    del uvs, texs, out4, out3
     torch.cuda.empty_cache()
     return res
 
@@ -398,6 +432,7 @@ def main():
         "gtris_s_submitted": round(scene.total_tri_instances / (h["ms"] * 1e-3) / 1e9, 4),
         "supersampling": h["supersampling"],
         "compressed": h["compressed"],
+        "textured_resolve": h["textured"],
     }
     st = h["stats"]
     result["stage_counts"] = {k: st[k] for k in ("culled_near", "culled_frustum", "culled_tiny", "culled_backface",
