@@ -1,0 +1,92 @@
+"""GPU edge cases of the rasterizer and resolve against the oracle (needs an MI355X): no meshes,
+meshes without triangles between others (ID bases), and views of 1 x 1, ragged sizes and the
+maximum width and height."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from helpers import assert_resolve_close, assert_vis_equal
+from paper_2604_21749_amd import api
+from paper_2604_21749_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = api.Context()
+    yield c
+    c.close()
+
+
+def _empty_mesh(n_instances=1):
+    inst = None
+    if n_instances > 1:
+        inst = np.tile(np.eye(3, 4, dtype=np.float32).reshape(1, 12), (n_instances, 1))
+    return W.Mesh(np.zeros((3, 3), np.float32), np.zeros((0, 3), np.uint32), inst=inst,
+                  attrs=np.zeros((3, 3), np.float32))
+
+
+def test_no_meshes_clears_the_view(ctx):
+    s = W.random_tiny_scene(1)
+    vis = ctx.rasterize_meshes([], s.views[0])
+    assert np.all(api.as_uint64(vis) == O.EMPTY)
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_meshes_without_triangles_keep_the_id_bases(graph):
+    """[empty, tiny instanced, empty x 3 instances, tiny, empty]: IDs skip nothing and the
+    resolve finds the right mesh."""
+    a = W.random_tiny_scene(7, n_instances=3, n_tris=20, spread=3.0)
+    b = W.random_tiny_scene(8, n_tris=12, near_crossing=True)
+    meshes = [_empty_mesh(), a.meshes[0], _empty_mesh(3), b.meshes[0], _empty_mesh()]
+    view = a.views[0]
+    flags = 0 if graph else api.FLAG_NO_GRAPH
+    with api.Context(flags=flags) as c:
+        gm = [api.GpuMesh.from_host(m) for m in meshes]
+        for _ in range(2):     # the second frame replays the captured graph
+            vis = c.rasterize_meshes(gm, view)
+            ref = O.rasterize(meshes, view)
+            assert_vis_equal(api.as_uint64(vis), ref, "meshes without triangles")
+        out = c.resolve(gm, view, vis, [g.attrs for g in gm]).cpu().numpy()
+        assert_resolve_close(out, O.resolve(meshes, view, ref, [m.attrs for m in meshes]), "resolve")
+
+
+@pytest.mark.parametrize("w,h", [(1, 1), (1, 37), (37, 1), (65, 65), (127, 3), (16384, 40), (40, 16384)])
+def test_view_sizes(ctx, w, h):
+    """Ragged tiles, single rows and columns, and the maximum width and height (16384)."""
+    for seed in range(3):
+        s = W.random_tiny_scene(100 + seed, n_tris=10, width=w, height=h, near_crossing=seed == 2, spread=2.0)
+        gm = [api.GpuMesh.from_host(m) for m in s.meshes]
+        vis = ctx.rasterize_meshes(gm, s.views[0])
+        ref = O.rasterize(s.meshes, s.views[0])
+        assert_vis_equal(api.as_uint64(vis), ref, f"{w}x{h} seed {seed}")
+        out = ctx.resolve(gm, s.views[0], vis, [g.attrs for g in gm]).cpu().numpy()
+        assert_resolve_close(out, O.resolve(s.meshes, s.views[0], ref, [m.attrs for m in s.meshes]), f"{w}x{h}")
+
+
+def test_maximum_view_16384_squared(ctx):
+    """A 16384 x 16384 view (2 GiB visibility buffer): few triangles, most of them large, so
+    stages 2 and 3 cover millions of pixels each."""
+    s = W.random_tiny_scene(200, n_tris=8, width=16384, height=16384, spread=1.0)
+    gm = [api.GpuMesh.from_host(m) for m in s.meshes]
+    vis = ctx.rasterize_meshes(gm, s.views[0])
+    ref = O.rasterize(s.meshes, s.views[0])
+    got = api.as_uint64(vis)
+    del vis
+    torch.cuda.empty_cache()
+    assert (ref != O.EMPTY).sum() > 10_000_000
+    assert_vis_equal(got, ref, "16384^2")
+
+
+def test_empty_compressed_mesh_renders_nothing(ctx):
+    a = W.random_tiny_scene(9, n_tris=16)
+    meshes = [_empty_mesh(), a.meshes[0]]
+    gm = [ctx.compress(api.GpuMesh.from_host(m)) for m in meshes]
+    vis = ctx.rasterize_meshes(gm, a.views[0])
+    lo_i, bits, words = O.compress_indices(a.meshes[0].idx)
+    lo, step = O.position_box(a.meshes[0].pos)
+    dm = O.decompressed_mesh(a.meshes[0], words, lo_i, bits, O.quantize_positions(a.meshes[0].pos, lo, step), lo,
+                             step)
+    assert_vis_equal(api.as_uint64(vis), O.rasterize([meshes[0], dm], a.views[0]), "empty compressed mesh")
