@@ -514,6 +514,19 @@ def test_position_quantization_bounds():
     # the box minimum decodes exactly, the maximum within one ulp
     i0 = np.argmin(pos[:, 0])
     assert q[i0, 0] == 0 and dec[i0, 0] == pos[i0, 0]
+    # decoding is q step + lo with one rounding (a fused multiply-add): exact rational value,
+    # rounded to the nearest binary32, ties to even
+    from fractions import Fraction
+    for c in range(2):
+        for i in range(0, 500, 7):
+            exact = Fraction(int(q[i, c])) * Fraction(float(step[c])) + Fraction(float(lo[c]))
+            f = np.float32(float(exact))
+            cands = [np.nextafter(f, np.float32(-np.inf)), f, np.nextafter(f, np.float32(np.inf))]
+            dist = [abs(Fraction(float(x)) - exact) for x in cands]
+            best = min(dist)
+            nearest = [x for x, d in zip(cands, dist) if d == best]
+            want = nearest[0] if len(nearest) == 1 else [x for x in nearest if (x.view(np.uint32) & 1) == 0][0]
+            assert dec[i, c] == want, (i, c)
 
 
 # ----------------------------------------------------------------------------------------------
@@ -593,6 +606,9 @@ def test_mip_chain_pins():
     cb = np.where((np.add.outer(np.arange(8), np.arange(8)) & 1) == 1, 0xFFFFFFFF, 0).astype(np.uint32)
     ch = O.build_mips(cb, 4)
     assert np.all(ch[64:] == 0x80808080)
+    # horizontal stripes (odd rows 255): both rows of each 2 x 2 block count, (0 + 0 + 255 + 255 + 2) >> 2
+    stripes = np.where((np.arange(8)[:, None] & 1) == 1, 0xFFFFFFFF, 0).repeat(4, axis=1).astype(np.uint32)
+    assert np.all(O.build_mips(stripes, 3)[32:] == 0x80808080)
     # by hand, a 4 x 1 row (rows clamped): [0, 1, 2, 5] -> [(0+1+0+1+2)>>2, (2+5+2+5+2)>>2] = [1, 4] -> [3]
     ch = O.build_mips(np.array([[0, 1, 2, 5]], np.uint32), 3)
     assert ch.tolist() == [0, 1, 2, 5, 1, 4, 3]
@@ -636,24 +652,35 @@ def test_texture_lod_pins():
 
 
 def test_textured_resolve_lod_closed_form():
-    """A fronto-parallel quad filling the view with u = k_u x + 1/2, v = k_v y + 1/2: adjacent pixels
-    are 1/16 world units apart at depth 2 (fovy 90, 64 px), so the footprint is s = 16 k_u 256 / 256
-    texels and the level of detail clamp(log2 s, 0, 8)."""
-    Wd = Hd = 64
+    """A fronto-parallel quad filling a 64 x 48 view with u = k_u x + 1/2, v = k_v y + 1/2: at depth
+    2 with fovy 90 the view is 4 world units high, so adjacent pixels are 1/12 apart in x and y and
+    the footprint is s = 256 k_u / 12 texels (k_v = k_u / 2), the level of detail clamp(log2 s, 0, 8)."""
+    Wd, Hd = 64, 48
     view = _view_cam(Wd, Hd, fovy=90.0)
-    quad = np.array([[-3, -3, -2], [3, -3, -2], [3, 3, -2], [-3, 3, -2]], np.float32)
+    quad = np.array([[-4, -3, -2], [4, -3, -2], [4, 3, -2], [-4, 3, -2]], np.float32)
     qidx = np.array([[0, 1, 2], [0, 2, 3]], np.uint32)
     mesh = W.Mesh(quad, qidx)
     vis = O.rasterize([mesh], view)
     assert np.all(vis != O.EMPTY)
     chain = _level_constant_chain(256, 256, 9)
     for s in (0.5, 1.0, 2.0, 3.3, 16.0, 1000.0):
-        ku = s / 16.0
+        ku = s * 12.0 / 256.0
         uv = np.stack([quad[:, 0] * ku + 0.5, quad[:, 1] * (ku / 2) + 0.5], axis=1).astype(np.float32)
         out = O.resolve_textured([mesh], view, vis, [uv], [(chain, 256, 256, 9)])
         expect = 20.0 * min(max(math.log2(s), 0.0), 8.0)
         assert np.max(np.abs(out[..., 0] * 255 - expect)) < 5e-3, s
         assert np.array_equal(out[..., 0], out[..., 1]) and np.all(out[..., 3] == out[..., 0])
+    # the uv of each pixel's own hit: u = 0.15 x + 1/2 and v = 0.2 y + 1/2 at the pixel centre,
+    # x = (2 (px + 1/2) / 64 - 1) 8/3 and y = (2 (py + 1/2) / 48 - 1) 2, read back through R / G ramps
+    uv = np.stack([quad[:, 0] * 0.15 + 0.5, quad[:, 1] * 0.2 + 0.5], axis=1).astype(np.float32)
+    ramp = (np.arange(256, dtype=np.uint32)[None, :] | (np.arange(256, dtype=np.uint32)[:, None] << 8))
+    out = O.resolve_textured([mesh], view, vis, [uv], [(O.build_mips(ramp, 1), 256, 256, 1)])
+    px = np.arange(Wd) + 0.5
+    py = np.arange(Hd) + 0.5
+    u = 0.15 * (2 * px / Wd - 1) * (8.0 / 3.0) + 0.5
+    v = 0.2 * (2 * py / Hd - 1) * 2.0 + 0.5
+    assert np.max(np.abs(out[..., 0] * 255 - (u[None, :] * 256 - 0.5))) < 2e-3
+    assert np.max(np.abs(out[..., 1] * 255 - (v[:, None] * 256 - 0.5))) < 2e-3
 
 
 def _ground_rays_f64(view, px, py, dx=0.5, dy=0.5):
