@@ -241,7 +241,7 @@ def stage1_rooflines(h):
     algorithmic lane-operations = ALU_OPS_PER_TRI_INST per triangle instance."""
     sm = h["stage_ms"]
     o = h["options"]
-    strips = "true" if (o["s1_multi_tris_per_thread"] in (2, 4) and not (o["flags"] & 0x100)) else "false"
+    strips = "true" if (o["s1_multi_tris_per_thread"] in (2, 4, 8) and not (o["flags"] & 0x100)) else "false"
     k_single = f"stage1_fast_kernel<{o['s1_block']}, {o['s1_tris_per_thread']}, false, false, 0>"
     k_multi = f"stage1_fast_kernel<{o['s1_block']}, {o['s1_multi_tris_per_thread']}, {strips}, false, 0>"
     single_bytes = stage1_algorithmic_bytes(h["single"])

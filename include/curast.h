@@ -106,9 +106,11 @@ typedef struct {
                                    with approximate reciprocals and wave-compacted exact work,
                                    3 = every mesh through the wave-level vertex-sharing kernel
                                    (each vertex transformed once per wave and draw) */
-    uint32_t s1_multi_tris_per_thread; /* as s1_tris_per_thread, for meshes with two or more
-                                   surviving draws, which stage 1 takes in a launch of its own
-                                   (default 4) */
+    uint32_t s1_multi_tris_per_thread; /* as s1_tris_per_thread (1, 2, 4 or 8; 1, 2 or 4 with
+                                   s1_mode 3), for meshes with two or more surviving draws, which
+                                   stage 1 takes in a launch of its own; with 2 or more, a lane's
+                                   consecutive triangles are tested as one strip when they form
+                                   one (default 4) */
 } curast_options;
 
 /*

@@ -182,7 +182,7 @@ extern "C" int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint3
         {&curast_options::s3_blocks, {cus, cus * 2, cus * 4}},
     };
     if (max_draws > 1) {
-        axes.push_back({&curast_options::s1_multi_tris_per_thread, {1, 2, 4}});
+        axes.push_back({&curast_options::s1_multi_tris_per_thread, {1, 2, 4, 8}});
         axes.push_back({&curast_options::s1_draws_per_item, {8, 16, 32, 64, 128, 256}});
     }
     for (int pass = 0; pass < 2; ++pass) {

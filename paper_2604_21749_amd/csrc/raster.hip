@@ -564,7 +564,7 @@ __device__ __forceinline__ bool in_tri(uint32_t v, const uint32_t (&t)[3]) { ret
 template <int S>
 __device__ __forceinline__ bool build_strip(const uint32_t (&t)[S][3], uint32_t (&v)[S + 2])
 {
-    static_assert(S == 2 || S == 4, "strips of 2 or 4 triangles");
+    static_assert(S == 2 || S == 4 || S == 8, "strips of 2, 4 or 8 triangles");
     bool ok = true;
     uint32_t out[S], nw[S];
 #pragma unroll
@@ -577,12 +577,13 @@ __device__ __forceinline__ bool build_strip(const uint32_t (&t)[S][3], uint32_t 
         v[2] = out[0] == t[0][0] ? t[0][2] : (out[0] == t[0][1] ? t[0][0] : t[0][1]);
         v[3] = nw[1];
     } else {
-        v[0] = out[0];
-        v[1] = out[1];
-        v[2] = out[2];
-        v[3] = nw[1];
-        v[4] = nw[2];
-        v[5] = nw[3];
+        // v_k is the vertex of triangle k that triangle k + 1 lacks (k <= S - 2); the last three are
+        // the vertices that triangles S - 3 .. S - 1 add to their predecessors
+#pragma unroll
+        for (int k = 0; k + 1 < S; ++k) v[k] = out[k];
+        v[S - 1] = nw[S - 3];
+        v[S] = nw[S - 2];
+        v[S + 1] = nw[S - 1];
     }
     // every triangle is exactly its three sequence vertices, all distinct
 #pragma unroll
@@ -610,7 +611,7 @@ __device__ __forceinline__ bool fast_reject_union(const float2 (&w)[N], const Vi
 template <int BLOCK, int TPT, bool STRIPS, bool STATS, int CMP>
 __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST_DESC_PARAMS)
 {
-    static_assert(!STRIPS || TPT == 2 || TPT == 4, "strips of 2 or 4 triangles per lane");
+    static_assert(!STRIPS || TPT == 2 || TPT == 4 || TPT == 8, "strips of 2, 4 or 8 triangles per lane");
     constexpr int WAVES = BLOCK / 64;
     using Entry = typename std::conditional<STRIPS, IdEntry, ClipEntry>::type;
     __shared__ Entry s_ring[WAVES][kRing];
@@ -1332,7 +1333,8 @@ static hipError_t stage1_fast_tpt(const RasterArgs& a, uint32_t tpt, bool strips
                           : stage1_fast_dispatch<BLOCK, 2, false>(a, stats, grid, s);
     case 4: return strips ? stage1_fast_dispatch<BLOCK, 4, true>(a, stats, grid, s)
                           : stage1_fast_dispatch<BLOCK, 4, false>(a, stats, grid, s);
-    case 8: return strips ? hipErrorInvalidValue : stage1_fast_dispatch<BLOCK, 8, false>(a, stats, grid, s);
+    case 8: return strips ? stage1_fast_dispatch<BLOCK, 8, true>(a, stats, grid, s)
+                          : stage1_fast_dispatch<BLOCK, 8, false>(a, stats, grid, s);
     default: return hipErrorInvalidValue;
     }
 }

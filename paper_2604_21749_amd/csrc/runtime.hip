@@ -135,8 +135,10 @@ int validate_options(const curast_options& o, std::string& msg)
         o.s1_tris_per_thread != 8)
         return bad("s1_tris_per_thread must be 1, 2, 4 or 8");
     if (o.s1_multi_tris_per_thread && o.s1_multi_tris_per_thread != 1 && o.s1_multi_tris_per_thread != 2 &&
-        o.s1_multi_tris_per_thread != 4)
-        return bad("s1_multi_tris_per_thread must be 1, 2 or 4");
+        o.s1_multi_tris_per_thread != 4 && o.s1_multi_tris_per_thread != 8)
+        return bad("s1_multi_tris_per_thread must be 1, 2, 4 or 8");
+    if (o.s1_mode == 3 && o.s1_multi_tris_per_thread == 8)
+        return bad("s1_mode 3 takes s1_multi_tris_per_thread 1, 2 or 4");
     if (o.small_px > 65536) return bad("small_px must be <= 65536");
     if (o.s1_mode > 3) return bad("s1_mode must be 0, 1, 2 or 3");
     if (o.s1_draws_per_item > 65536) return bad("s1_draws_per_item must be <= 65536");
@@ -644,7 +646,7 @@ int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, uint32_t grid_s
             a1.part = part;
             if (part == 1 && mode == 3) return launch_stage1_share(a1, tpt, stats, grid, s);
             if (mode == 1) return launch_stage1(a1, blk, tpt, stats, grid, s);
-            const bool strips = !(ctx->opt.flags & kFlagNoStrips) && (tpt == 2 || tpt == 4) &&
+            const bool strips = !(ctx->opt.flags & kFlagNoStrips) && tpt >= 2 &&
                                 (part == 1 || (ctx->opt.flags & kFlagSingleStrips));
             return launch_stage1_fast(a1, blk, tpt, strips, stats, grid, s);
         };

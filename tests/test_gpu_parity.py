@@ -94,6 +94,8 @@ OPTION_SWEEP = [
     dict(flags=api.FLAG_SINGLE_STRIPS | api.FLAG_NO_TINY_CULL, small_px=1),
     dict(s1_tris_per_thread=8), dict(s1_tris_per_thread=8, s1_block=512, s1_mode=1),
     dict(s1_tris_per_thread=8, s1_block=64, flags=api.FLAG_SINGLE_STRIPS),
+    dict(s1_multi_tris_per_thread=8), dict(s1_multi_tris_per_thread=8, s1_block=64, flags=api.FLAG_NO_FAST_INTERIOR),
+    dict(s1_multi_tris_per_thread=8, s1_block=512, s1_draws_per_item=3, flags=api.FLAG_STATS),
 ]
 
 
@@ -201,10 +203,12 @@ def _strip_scene(seed):
     dict(flags=api.FLAG_NO_STRIPS | api.FLAG_NO_FAST_INTERIOR), dict(s1_multi_tris_per_thread=4),
     dict(s1_multi_tris_per_thread=4, s1_block=64), dict(s1_multi_tris_per_thread=2, s1_block=512),
     dict(flags=api.FLAG_NO_TINY_CULL), dict(s1_mode=2, small_px=1, medium_px=1),
-    dict(flags=api.FLAG_SINGLE_STRIPS, s1_draws_per_item=3),
+    dict(flags=api.FLAG_SINGLE_STRIPS, s1_draws_per_item=3), dict(s1_multi_tris_per_thread=8),
+    dict(s1_multi_tris_per_thread=8, s1_block=64, s1_draws_per_item=5),
+    dict(s1_multi_tris_per_thread=8, flags=api.FLAG_SINGLE_STRIPS, s1_tris_per_thread=8),
 ])
 def test_strips_and_interior_draws(opts):
-    """The strip path (shared window positions and one union-box test per strip of 2 or 4
+    """The strip path (shared window positions and one union-box test per strip of 2, 4 or 8
     triangles) and the prescaled interior rows reject only what the exact path would:
     bit-identical to the oracle."""
     with api.Context(**opts) as c:
