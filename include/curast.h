@@ -94,10 +94,10 @@ typedef struct {
     uint32_t s1_tris_per_thread;/* triangles per thread per stage-1 work item of a mesh drawn once:
                                    1, 2, 4 or 8 (default 4) */
     uint32_t s1_draws_per_item; /* (instance x view) draws per stage-1 work item (default 64, Sec. 4.5) */
-    uint32_t s2_waves;          /* persistent stage-2 wavefronts (default 4 per CU) */
+    uint32_t s2_waves;          /* persistent stage-2 wavefronts (default 16 per CU) */
     uint32_t s3_blocks;         /* persistent stage-3 workgroups (default 2 per CU) */
-    uint32_t q2_capacity;       /* stage-1 -> stage-2 queue entries (default 1M); overflow is
-                                   rasterized in place, never dropped */
+    uint32_t q2_capacity;       /* stage-1 -> stage-2 queue entries (default 16M, 128 MB); overflow
+                                   is rasterized in place, never dropped */
     uint32_t q3_capacity;       /* stage-2 -> stage-3 tile parts (default 1M); overflow as above */
     uint32_t large_capacity;    /* large (sub-)triangle records for stage 3 (default 256K) */
     uint32_t flags;             /* CURAST_FLAG_* */

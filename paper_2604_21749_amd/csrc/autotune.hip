@@ -178,7 +178,7 @@ extern "C" int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint3
         {&curast_options::s1_tris_per_thread, {1, 2, 4, 8}},
         {&curast_options::small_px, {32, 64, 128, 256, 512}},
         {&curast_options::medium_px, {1024, 4096, 16384}},
-        {&curast_options::s2_waves, {cus * 2, cus * 4, cus * 8}},
+        {&curast_options::s2_waves, {cus * 4, cus * 8, cus * 16, cus * 32}},
         {&curast_options::s3_blocks, {cus, cus * 2, cus * 4}},
     };
     if (max_draws > 1) {

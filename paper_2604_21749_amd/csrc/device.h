@@ -270,12 +270,14 @@ __device__ inline bool setup_tri64(const int32_t X[3], const int32_t Y[3], const
     return true;
 }
 
-// Edge value E_k at the centre of pixel (px, py).
+// Edge value E_k at the centre of pixel (px, py).  Snapped coordinates lie in the guard band
+// (|X| < 17 * 8192 * 256 < 2^26) and pixel centres below 2^22, so the differences and the edge
+// vectors fit int32 and each product is one 32 x 32 -> 64-bit multiply.
 __device__ __forceinline__ int64_t edge64(const Tri64& t, int k, int32_t px, int32_t py)
 {
     const int a = k == 2 ? 0 : k + 1;
-    const int64_t Px = 256 * (int64_t)px + 128, Py = 256 * (int64_t)py + 128;
-    return (int64_t)t.dx[k] * (Py - t.Y[a]) - (int64_t)t.dy[k] * (Px - t.X[a]);
+    const int32_t rx = 256 * px + 128 - t.X[a], ry = 256 * py + 128 - t.Y[a];
+    return (int64_t)t.dx[k] * (int64_t)ry - (int64_t)t.dy[k] * (int64_t)rx;
 }
 
 // Test one pixel of a general triangle and write its fragment.

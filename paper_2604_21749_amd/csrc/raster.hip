@@ -1017,111 +1017,184 @@ __global__ void __launch_bounds__(256) stage1_overflow_kernel(RasterArgs a, CURA
 }
 
 // ----------------------------------------------------------------------------------------------
+// One wavefront rasterizes a general triangle over its clamped box, visiting only blocks of 64
+// pixels that can hold a covered pixel centre.  The box is cut into blocks as square as its
+// shape allows (8 x 8, or 1/2/4 wide for narrow boxes, 1/2/4 high for flat ones).  First every
+// lane tests one block: an edge function is affine, so its maximum over the block's pixel
+// centres sits at one corner (the left or right column as the edge's dy is positive or not, the
+// top or bottom row as its dx is positive or not); a block whose maximum E_k + bias_k is
+// negative for some edge holds no covered centre.  The test is exact (int64), so skipping such
+// blocks changes nothing.  Then the wave visits the remaining blocks one by one, one pixel per
+// lane, with the usual per-pixel test.
+// ----------------------------------------------------------------------------------------------
+template <class Stats>
+__device__ __forceinline__ void raster_wave_blocks(const Tri64& t, uint64_t id, unsigned long long* vis, int32_t W,
+                                                   bool early_out, uint32_t lane, Stats& st)
+{
+    const uint32_t bw = (uint32_t)(t.px1 - t.px0 + 1), bh = (uint32_t)(t.py1 - t.py0 + 1);
+    uint32_t lbw;   // log2 of the block width; the block is 64 pixels
+    if (bw >= 8 && bh >= 8) lbw = 3;
+    else if (bw < 8) lbw = bw <= 1 ? 0 : bw <= 2 ? 1 : bw <= 4 ? 2 : 3;
+    else lbw = bh <= 1 ? 6 : bh <= 2 ? 5 : bh <= 4 ? 4 : 3;
+    const uint32_t BW = 1u << lbw, lbh = 6 - lbw;
+    const uint32_t nbx = (bw + BW - 1) >> lbw, nby = (bh + (1u << lbh) - 1) >> lbh;
+    const uint32_t nblocks = nbx * nby;
+    for (uint32_t base = 0; base < nblocks; base += 64) {
+        const uint32_t j = base + lane;
+        bool cand = false;
+        if (j < nblocks) {
+            const uint32_t by = j / nbx, bx = j - by * nbx;
+            const int32_t x0 = t.px0 + (int32_t)(bx << lbw), y0 = t.py0 + (int32_t)(by << lbh);
+            const int32_t x1 = min(x0 + (int32_t)BW - 1, t.px1), y1 = min(y0 + (1 << lbh) - 1, t.py1);
+            cand = true;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int32_t cx = t.dy[k] > 0 ? x0 : x1;
+                const int32_t cy = t.dx[k] > 0 ? y1 : y0;
+                cand = cand && edge64(t, k, cx, cy) + t.bias[k] >= 0;
+            }
+        }
+        unsigned long long mask = __ballot(cand);
+        while (mask) {
+            const uint32_t jb = base + (uint32_t)__builtin_ctzll(mask);
+            mask &= mask - 1;
+            const uint32_t by = jb / nbx, bx = jb - by * nbx;
+            const int32_t px = t.px0 + (int32_t)((bx << lbw) + (lane & (BW - 1)));
+            const int32_t py = t.py0 + (int32_t)((by << lbh) + (lane >> lbw));
+            if (px <= t.px1 && py <= t.py1 && raster_pixel64(t, px, py, id, vis, W, early_out)) st.add(kStFragments);
+        }
+    }
+}
+
+// ----------------------------------------------------------------------------------------------
 // Stage 2: one wavefront per forwarded triangle (Sec. 4.2)
 // ----------------------------------------------------------------------------------------------
+// Snapped polygon of one forwarded triangle (3 vertices, or up to 8 after clipping), in LDS.
+struct S2Poly {
+    int32_t X[8], Y[8];
+    float zI[8];
+    uint64_t id;
+    uint32_t np, view;
+};
+
 template <bool STATS>
 __global__ void __launch_bounds__(256) stage2_kernel(RasterArgs a)
 {
+    // Each wavefront takes 64 queue entries at a time.  Every lane sets up one of them (descriptor,
+    // index and vertex loads, transform, clip, snap: 64 dependent load chains in flight at once)
+    // and leaves the snapped polygon in LDS; then the whole wavefront rasterizes the 64 polygons
+    // one after the other.
+    __shared__ S2Poly s_poly[4][64];
     const uint32_t lane = threadIdx.x & 63;
+    const uint32_t wslot = threadIdx.x >> 6;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
     const unsigned long long n = min(a.counters[kCntQ2], (unsigned long long)a.q2_cap);
     const bool early_out = !(a.flags & kFlagNoEarlyOut);
     StatAcc<STATS> st;
-    for (unsigned long long e = wave; e < n; e += nwaves) {
-        const Q2Entry q = a.q2[e];
-        const uint32_t d = __builtin_amdgcn_readfirstlane(q.draw);
-        const uint32_t t = __builtin_amdgcn_readfirstlane(q.tri);
-        const DrawDesc& D = a.draws[d];
-        const ViewDesc V = a.views[D.view & kDrawViewMask];
-        const MeshDesc M = a.meshes[D.mesh];
-        const uint64_t id = D.id_base + t;
-        Clip c[3];
-        uint32_t iv[3];
-        mesh_triangle(M, t, iv);
-        for (int k = 0; k < 3; ++k) {
-            float q[3];
-            mesh_vertex(M, iv[k], q);
-            c[k] = transform(D.A, q[0], q[1], q[2]);
+    for (unsigned long long base = (unsigned long long)wave * 64; base < n; base += (unsigned long long)nwaves * 64) {
+        S2Poly& mine = s_poly[wslot][lane];
+        const unsigned long long e = base + lane;
+        uint32_t np = 0;
+        if (e < n) {
+            const Q2Entry q = a.q2[e];
+            const DrawDesc& D = a.draws[q.draw];
+            const uint32_t view = D.view & kDrawViewMask;
+            const ViewDesc& V = a.views[view];
+            const MeshDesc& M = a.meshes[D.mesh];
+            Clip c[3];
+            uint32_t iv[3];
+            mesh_triangle(M, q.tri, iv);
+            for (int k = 0; k < 3; ++k) {
+                float qv[3];
+                mesh_vertex(M, iv[k], qv);
+                c[k] = transform(D.A, qv[0], qv[1], qv[2]);
+            }
+            const float hW = V.hW, hH = V.hH;
+            if (outside_guard(c[0], V.near_plane) || outside_guard(c[1], V.near_plane) ||
+                outside_guard(c[2], V.near_plane)) {
+                Clip poly[8];
+                np = (uint32_t)clip_triangle(c, V.near_plane, poly);
+                for (uint32_t k = 0; k < np; ++k) snap_vertex(poly[k], hW, hH, mine.X[k], mine.Y[k], mine.zI[k]);
+            } else {
+                np = 3;
+                for (int k = 0; k < 3; ++k) snap_vertex(c[k], hW, hH, mine.X[k], mine.Y[k], mine.zI[k]);
+            }
+            mine.id = D.id_base + q.tri;
+            mine.view = view;
         }
-        Clip poly[8];
-        int np = 3;
-        if (outside_guard(c[0], V.near_plane) || outside_guard(c[1], V.near_plane) ||
-            outside_guard(c[2], V.near_plane)) {
-            np = clip_triangle(c, V.near_plane, poly);
-        } else {
-            poly[0] = c[0];
-            poly[1] = c[1];
-            poly[2] = c[2];
-        }
-        int32_t X[8], Y[8];
-        float zI[8];
-        for (int k = 0; k < np; ++k) snap_vertex(poly[k], V.hW, V.hH, X[k], Y[k], zI[k]);
-        for (int j = 1; j + 1 < np; ++j) {
-            const int32_t tx[3] = {X[0], X[j], X[j + 1]}, ty[3] = {Y[0], Y[j], Y[j + 1]};
-            const float tz[3] = {zI[0], zI[j], zI[j + 1]};
-            Tri64 tri;
-            if (!setup_tri64(tx, ty, tz, V.W, V.H, tri)) continue;
-            const uint32_t bw = (uint32_t)(tri.px1 - tri.px0 + 1);
-            const uint64_t cnt = (uint64_t)bw * (uint64_t)(tri.py1 - tri.py0 + 1);
-            bool in_place = cnt <= a.medium_px;
-            if (!in_place) {
-                const uint32_t tx0 = tri.px0 / kTileSize, tx1 = tri.px1 / kTileSize;
-                const uint32_t ty0 = tri.py0 / kTileSize, ty1 = tri.py1 / kTileSize;
-                const uint32_t ntx = tx1 - tx0 + 1;
-                const uint64_t ntiles = (uint64_t)ntx * (uint64_t)(ty1 - ty0 + 1);
-                unsigned long long rec = 0, qbase = 0;
-                if (lane == 0) {
-                    rec = atomicAdd(a.counters + kCntLarge, 1ull);
-                    qbase = atomicAdd(a.counters + kCntQ3, (unsigned long long)ntiles);
-                }
-                rec = __shfl(rec, 0);
-                qbase = __shfl(qbase, 0);
-                const bool ok = rec < a.large_cap && qbase + ntiles <= a.q3_cap;
-                if (ok) {
+        mine.np = np;
+        wave_lds_sync();
+        for (uint32_t l = 0; l < 64; ++l) {
+            const S2Poly& P = s_poly[wslot][l];
+            const uint32_t npl = __builtin_amdgcn_readfirstlane(P.np);
+            if (npl < 3) continue;
+            const uint32_t view = __builtin_amdgcn_readfirstlane(P.view);
+            const ViewDesc V = a.views[view];
+            const uint64_t id = P.id;
+            for (uint32_t j = 1; j + 1 < npl; ++j) {
+                const int32_t tx[3] = {P.X[0], P.X[j], P.X[j + 1]}, ty[3] = {P.Y[0], P.Y[j], P.Y[j + 1]};
+                const float tz[3] = {P.zI[0], P.zI[j], P.zI[j + 1]};
+                Tri64 tri;
+                if (!setup_tri64(tx, ty, tz, V.W, V.H, tri)) continue;
+                const uint32_t bw = (uint32_t)(tri.px1 - tri.px0 + 1);
+                const uint64_t cnt = (uint64_t)bw * (uint64_t)(tri.py1 - tri.py0 + 1);
+                bool in_place = cnt <= a.medium_px;
+                if (!in_place) {
+                    const uint32_t tx0 = tri.px0 / kTileSize, tx1 = tri.px1 / kTileSize;
+                    const uint32_t ty0 = tri.py0 / kTileSize, ty1 = tri.py1 / kTileSize;
+                    const uint32_t ntx = tx1 - tx0 + 1;
+                    const uint64_t ntiles = (uint64_t)ntx * (uint64_t)(ty1 - ty0 + 1);
+                    unsigned long long rec = 0, qbase = 0;
                     if (lane == 0) {
-                        LargeTri r;
-                        for (int k = 0; k < 3; ++k) {
-                            r.X[k] = tx[k];
-                            r.Y[k] = ty[k];
-                            r.zI[k] = tz[k];
+                        rec = atomicAdd(a.counters + kCntLarge, 1ull);
+                        qbase = atomicAdd(a.counters + kCntQ3, (unsigned long long)ntiles);
+                    }
+                    rec = __shfl(rec, 0);
+                    qbase = __shfl(qbase, 0);
+                    const bool ok = rec < a.large_cap && qbase + ntiles <= a.q3_cap;
+                    if (ok) {
+                        if (lane == 0) {
+                            LargeTri r;
+                            for (int k = 0; k < 3; ++k) {
+                                r.X[k] = tx[k];
+                                r.Y[k] = ty[k];
+                                r.zI[k] = tz[k];
+                            }
+                            r.view = view;
+                            r.id = id;
+                            a.large[rec] = r;
                         }
-                        r.view = D.view & kDrawViewMask;
-                        r.id = id;
-                        a.large[rec] = r;
+                        const uint32_t view_ntx = (uint32_t)(V.W + kTileSize - 1) / kTileSize;
+                        for (uint64_t i = lane; i < ntiles; i += 64) {
+                            Q3Entry qe;
+                            qe.rec = (uint32_t)rec;
+                            qe.tx = (uint16_t)(tx0 + (uint32_t)(i % ntx));
+                            qe.ty = (uint16_t)(ty0 + (uint32_t)(i / ntx));
+                            a.q3[qbase + i] = qe;
+                            atomicAdd(a.tile_count + V.tile_base + (uint32_t)qe.ty * view_ntx + qe.tx, 1u);
+                        }
+                        if (lane == 0) st.add(kStQ3, (uint32_t)ntiles);
+                    } else {
+                        // the reserved range may start inside the queue: mark those slots empty
+                        for (uint64_t i = lane; i < ntiles && qbase + i < a.q3_cap; i += 64) {
+                            Q3Entry qe;
+                            qe.rec = kNullRecord;
+                            qe.tx = 0;
+                            qe.ty = 0;
+                            a.q3[qbase + i] = qe;
+                        }
+                        if (lane == 0) st.add(kStQ3Overflow);
+                        in_place = true;
                     }
-                    const uint32_t view_ntx = (uint32_t)(V.W + kTileSize - 1) / kTileSize;
-                    for (uint64_t i = lane; i < ntiles; i += 64) {
-                        Q3Entry qe;
-                        qe.rec = (uint32_t)rec;
-                        qe.tx = (uint16_t)(tx0 + (uint32_t)(i % ntx));
-                        qe.ty = (uint16_t)(ty0 + (uint32_t)(i / ntx));
-                        a.q3[qbase + i] = qe;
-                        atomicAdd(a.tile_count + V.tile_base + (uint32_t)qe.ty * view_ntx + qe.tx, 1u);
-                    }
-                    if (lane == 0) st.add(kStQ3, (uint32_t)ntiles);
-                } else {
-                    // the reserved range may start inside the queue: mark those slots empty
-                    for (uint64_t i = lane; i < ntiles && qbase + i < a.q3_cap; i += 64) {
-                        Q3Entry qe;
-                        qe.rec = kNullRecord;
-                        qe.tx = 0;
-                        qe.ty = 0;
-                        a.q3[qbase + i] = qe;
-                    }
-                    if (lane == 0) st.add(kStQ3Overflow);
-                    in_place = true;
                 }
-            }
-            if (in_place) {
-                if (lane == 0) st.add(kStS2Raster);
-                for (uint64_t i = lane; i < cnt; i += 64) {
-                    const int32_t px = tri.px0 + (int32_t)(i % bw);
-                    const int32_t py = tri.py0 + (int32_t)(i / bw);
-                    if (raster_pixel64(tri, px, py, id, V.vis, V.W, early_out)) st.add(kStFragments);
+                if (in_place) {
+                    if (lane == 0) st.add(kStS2Raster);
+                    raster_wave_blocks(tri, id, V.vis, V.W, early_out, lane, st);
                 }
             }
         }
+        wave_lds_sync();   // the polygons are read by every lane before the next round overwrites them
     }
     st.flush(a.stats);
 }

@@ -156,9 +156,9 @@ curast_options resolve_defaults(const curast_options& u, int cus)
     if (!o.s1_tris_per_thread) o.s1_tris_per_thread = 4;
     if (!o.s1_multi_tris_per_thread) o.s1_multi_tris_per_thread = 4;
     if (!o.s1_draws_per_item) o.s1_draws_per_item = 64;
-    if (!o.s2_waves) o.s2_waves = (uint32_t)cus * 4;
+    if (!o.s2_waves) o.s2_waves = (uint32_t)cus * 16;
     if (!o.s3_blocks) o.s3_blocks = (uint32_t)cus * 2;
-    if (!o.q2_capacity) o.q2_capacity = 1u << 20;
+    if (!o.q2_capacity) o.q2_capacity = 1u << 24;
     if (!o.q3_capacity) o.q3_capacity = 1u << 20;
     if (!o.large_capacity) o.large_capacity = 1u << 18;
     return o;
