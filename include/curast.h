@@ -88,7 +88,8 @@ typedef enum {
 
 /* Tuning knobs; 0 selects the default (or the autotuned value).  None of them changes results. */
 typedef struct {
-    uint32_t small_px;          /* stage-1 limit on pixel centres in the clamped bbox (default 128, Sec. 4) */
+    uint32_t small_px;          /* stage-1 limit on pixel centres in the clamped bbox (default 32; the
+                                   paper's 128, Sec. 4, measured slower here) */
     uint32_t medium_px;         /* stage-2 limit (default 4096, Sec. 4) */
     uint32_t s1_block;          /* stage-1 workgroup size: 64, 128, 256 or 512 (default 128, Sec. 4.1) */
     uint32_t s1_tris_per_thread;/* triangles per thread per stage-1 work item of a mesh drawn once:

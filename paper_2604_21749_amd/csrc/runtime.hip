@@ -150,7 +150,7 @@ int validate_options(const curast_options& o, std::string& msg)
 curast_options resolve_defaults(const curast_options& u, int cus)
 {
     curast_options o = u;
-    if (!o.small_px) o.small_px = 128;
+    if (!o.small_px) o.small_px = 32;
     if (!o.medium_px) o.medium_px = 4096;
     if (!o.s1_block) o.s1_block = 128;
     if (!o.s1_tris_per_thread) o.s1_tris_per_thread = 4;
