@@ -91,7 +91,7 @@ typedef struct {
     uint32_t small_px;          /* stage-1 limit on pixel centres in the clamped bbox (default 32; the
                                    paper's 128, Sec. 4, measured slower here) */
     uint32_t medium_px;         /* stage-2 limit (default 4096, Sec. 4) */
-    uint32_t s1_block;          /* stage-1 workgroup size: 64, 128, 256 or 512 (default 128, Sec. 4.1) */
+    uint32_t s1_block;          /* stage-1 workgroup size: 64, 128, 256 or 512 (default 64, Sec. 4.1) */
     uint32_t s1_tris_per_thread;/* triangles per thread per stage-1 work item of a mesh drawn once:
                                    1, 2, 4 or 8 (default 4) */
     uint32_t s1_draws_per_item; /* (instance x view) draws per stage-1 work item (default 64, Sec. 4.5) */
@@ -112,6 +112,8 @@ typedef struct {
                                    stage 1 takes in a launch of its own; with 2 or more, a lane's
                                    consecutive triangles are tested as one strip when they form
                                    one (default 4) */
+    uint32_t s1_blocks_per_cu;  /* stage-1 grid: at most this many workgroups per compute unit per
+                                   launch, each looping over work items (default 2048, 1..65536) */
 } curast_options;
 
 /*

@@ -46,7 +46,7 @@ class Options(C.Structure):
     _fields_ = [(n, C.c_uint32) for n in (
         "small_px", "medium_px", "s1_block", "s1_tris_per_thread", "s1_draws_per_item", "s2_waves",
         "s3_blocks", "q2_capacity", "q3_capacity", "large_capacity", "flags", "s1_mode",
-        "s1_multi_tris_per_thread")]
+        "s1_multi_tris_per_thread", "s1_blocks_per_cu")]
 
 
 class CompressedStruct(C.Structure):

@@ -62,6 +62,7 @@ const Field kFields[] = {
     {"large_capacity", &curast_options::large_capacity},
     {"s1_mode", &curast_options::s1_mode},
     {"s1_multi_tris_per_thread", &curast_options::s1_multi_tris_per_thread},
+    {"s1_blocks_per_cu", &curast_options::s1_blocks_per_cu},
 };
 
 std::string to_json(const std::string& key, const curast_options& o)
@@ -176,6 +177,7 @@ extern "C" int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint3
         {&curast_options::s1_mode, {0, 1, 2, 3}},
         {&curast_options::s1_block, {64, 128, 256, 512}},
         {&curast_options::s1_tris_per_thread, {1, 2, 4, 8}},
+        {&curast_options::s1_blocks_per_cu, {256, 1024, 2048, 4096}},
         {&curast_options::small_px, {32, 64, 128, 256, 512}},
         {&curast_options::medium_px, {1024, 4096, 16384}},
         {&curast_options::s2_waves, {cus * 4, cus * 8, cus * 16, cus * 32}},

@@ -1,6 +1,7 @@
 // Rasterization kernels for gfx950: clear, stage 1 (one lane per small triangle), the stage-1
-// overflow pass, stage 2 (one wavefront per medium triangle, clipping) and stage 3 (one workgroup
-// per 64x64 tile part of a large triangle).  Sec. 4.1-4.3 describe the three stages; the wave64
+// overflow pass, stage 2 (a wavefront sets up 64 medium triangles in parallel, clipping them, then
+// rasterizes them one by one) and stage 3 (one workgroup per 64x64 tile part of a large
+// triangle).  Sec. 4.1-4.3 describe the three stages; the wave64
 // mapping, ballot-compacted queues and in-place overflow handling are this implementation's.
 #include <hip/hip_runtime.h>
 
@@ -1067,7 +1068,8 @@ __device__ __forceinline__ void raster_wave_blocks(const Tri64& t, uint64_t id, 
 }
 
 // ----------------------------------------------------------------------------------------------
-// Stage 2: one wavefront per forwarded triangle (Sec. 4.2)
+// Stage 2: the wavefront rasterizes forwarded triangles one at a time (Sec. 4.2), after setting up
+// 64 of them in parallel
 // ----------------------------------------------------------------------------------------------
 // Snapped polygon of one forwarded triangle (3 vertices, or up to 8 after clipping), in LDS.
 struct S2Poly {

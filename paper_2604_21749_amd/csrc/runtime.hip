@@ -70,7 +70,7 @@ struct Staging {
 };
 
 struct GraphEntry {
-    uint64_t key[9];
+    uint64_t key[10];
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -142,6 +142,7 @@ int validate_options(const curast_options& o, std::string& msg)
     if (o.small_px > 65536) return bad("small_px must be <= 65536");
     if (o.s1_mode > 3) return bad("s1_mode must be 0, 1, 2 or 3");
     if (o.s1_draws_per_item > 65536) return bad("s1_draws_per_item must be <= 65536");
+    if (o.s1_blocks_per_cu > 65536) return bad("s1_blocks_per_cu must be <= 65536");
     if (o.q2_capacity > (1u << 30) || o.q3_capacity > (1u << 30) || o.large_capacity > (1u << 28))
         return bad("queue capacity too large");
     return CURAST_OK;
@@ -152,10 +153,11 @@ curast_options resolve_defaults(const curast_options& u, int cus)
     curast_options o = u;
     if (!o.small_px) o.small_px = 32;
     if (!o.medium_px) o.medium_px = 4096;
-    if (!o.s1_block) o.s1_block = 128;
+    if (!o.s1_block) o.s1_block = 64;
     if (!o.s1_tris_per_thread) o.s1_tris_per_thread = 4;
     if (!o.s1_multi_tris_per_thread) o.s1_multi_tris_per_thread = 4;
     if (!o.s1_draws_per_item) o.s1_draws_per_item = 64;
+    if (!o.s1_blocks_per_cu) o.s1_blocks_per_cu = 2048;
     if (!o.s2_waves) o.s2_waves = (uint32_t)cus * 16;
     if (!o.s3_blocks) o.s3_blocks = (uint32_t)cus * 2;
     if (!o.q2_capacity) o.q2_capacity = 1u << 24;
@@ -640,8 +642,13 @@ int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, uint32_t grid_s
         // work items [0, shared_batches) are the multi-draw meshes' (part 1), the rest part 2; each
         // launch's kernel processes s1_block x (its tris-per-thread) triangles per work item,
         // matching the batch size the plan gave those segments
+        // each launch has at most s1_blocks_per_cu workgroups per CU, which loop over the work
+        // items: a workgroup's set-up is then shared by several items, and the dispatcher
+        // launches fewer workgroups (one per item measured slower on the HBM-bound launch)
         const uint32_t mode = ctx->opt.s1_mode, blk = ctx->opt.s1_block;
+        const uint32_t grid_cap = (uint32_t)std::min<uint64_t>((uint64_t)cus * ctx->opt.s1_blocks_per_cu, 1ull << 24);
         auto launch_part = [&](uint32_t part, uint32_t tpt, uint32_t grid) {
+            grid = std::min(grid, grid_cap);
             RasterArgs a1 = a;
             a1.part = part;
             if (part == 1 && mode == 3) return launch_stage1_share(a1, tpt, stats, grid, s);
@@ -706,13 +713,13 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
     // graph path: one captured sequence per structure (sizes of the descriptor block, grid bound,
     // options); replays copy the new descriptor contents from the same pinned buffer
     const uint32_t grid1 = grid_for(P.max_batches);
-    uint64_t key[9] = {(uint64_t)M, (uint64_t)n_views, (uint64_t)P.max_bytes, (uint64_t)grid1,
+    uint64_t key[10] = {(uint64_t)M, (uint64_t)n_views, (uint64_t)P.max_bytes, (uint64_t)grid1,
                        ((uint64_t)ctx->opt.s1_block << 32) | (ctx->opt.s1_tris_per_thread << 8) |
                            (ctx->opt.s1_multi_tris_per_thread << 4) | ctx->opt.s1_mode,
                        ((uint64_t)ctx->opt.s2_waves << 32) | ctx->opt.s3_blocks,
                        ((uint64_t)ctx->opt.flags << 32) | ctx->opt.small_px,
                        ((uint64_t)ctx->opt.medium_px << 32) | ctx->opt.s1_draws_per_item,
-                       ((uint64_t)P.compressed << 32) | P.compressed_parts};
+                       ((uint64_t)P.compressed << 32) | P.compressed_parts, (uint64_t)ctx->opt.s1_blocks_per_cu};
     GraphEntry* ge = nullptr;
     for (auto& g : ctx->graphs)
         if (std::memcmp(g.key, key, sizeof key) == 0) ge = &g;
