@@ -212,19 +212,20 @@ def run_textured(args, api, torch, W, ctx, gm, attrs, view, vis):
     return res
 
 
-def read_traffic(kernel: str):
+def read_traffic(kernel: str, path: str = "", src_path: str = ""):
     """HBM bytes per launch of a kernel from the committed profiler summary, if it was taken from
     the current kernel source (else None: the counters no longer describe the kernel)."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "stage1_c3_traffic.txt")
+    path = path or os.path.join(ROOT, "profiles", "stage1_c3_traffic.txt")
+    src_path = src_path or os.path.join(ROOT, "paper_2604_21749_amd", "csrc", "raster.hip")
     if not os.path.exists(path):
         return None
-    src = open(os.path.join(ROOT, "paper_2604_21749_amd", "csrc", "raster.hip"), "rb").read()
+    src = open(src_path, "rb").read()
     sha = hashlib.sha256(src).hexdigest()[:16]
     fields = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
-            k, v = line.split(":", 1)
+            k, v = line.rsplit(":", 1)          # keys may hold a colon ("sha256[:16]"), values do not
             fields[k.strip()] = v.strip()
     if fields.get("raster.hip sha256[:16]") != sha:
         return None
