@@ -609,6 +609,14 @@ __device__ __forceinline__ bool fast_reject_union(const float2 (&w)[N], const Vi
     return fast_reject_extent(x0, x1, y0, y1, V, tiny_cull);
 }
 
+// A strip whose union box may hold a pixel centre, waiting for its per-triangle tests: the
+// window positions of its N vertices for one draw, the draw and its first triangle.
+template <int N>
+struct StripEntry {
+    float2 w[N];
+    uint32_t draw, tri;
+};
+
 template <int BLOCK, int TPT, bool STRIPS, bool STATS, int CMP>
 __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST_DESC_PARAMS)
 {
@@ -616,6 +624,11 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
     constexpr int WAVES = BLOCK / 64;
     using Entry = typename std::conditional<STRIPS, IdEntry, ClipEntry>::type;
     __shared__ Entry s_ring[WAVES][kRing];
+    // strips that fail the union test gather here, 64 at a time, so that their per-triangle tests
+    // run with every lane busy instead of on the few failing lanes of a draw
+    __shared__ StripEntry<TPT + 2> s_strip[WAVES][STRIPS ? kRing : 1];
+    StripEntry<TPT + 2>* sring = s_strip[threadIdx.x >> 6];
+    uint32_t shead = 0, stail = 0;   // wave-uniform
     const FrameHeader hdr = *d_hdr;
     uint64_t first, total;
     work_range(hdr, a.part, first, total);
@@ -627,7 +640,7 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
     uint32_t head = 0, tail = 0;   // wave-uniform
     StatAcc<STATS> st;
     // append (draw d, triangle t) where `need`; fill(e) writes the rest of the entry
-    auto push = [&](bool need, uint32_t d, uint32_t t, auto&& fill) {
+    auto push = [&](bool need, uint32_t d, uint32_t t, auto&& fill) __attribute__((always_inline)) {
         const unsigned long long m = __ballot(need);
         if (m) {
             if (need) {
@@ -660,6 +673,27 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
     auto reject = [&](auto interior_tag, float2 x, float2 y, float2 z, const ViewDesc& V) -> bool {
         if constexpr (decltype(interior_tag)::value) return fast_reject_box(x, y, z, V, tiny_cull);
         else return fast_reject(x, y, z, V, tiny_cull);
+    };
+    // per-triangle tests of n gathered strips, one strip per lane; survivors go to the exact path
+    auto drain_strips = [&](uint32_t n) __attribute__((always_inline)) {
+        if constexpr (STRIPS) {
+            const uint32_t lane = threadIdx.x & 63;
+            const bool have = lane < n;
+            const StripEntry<TPT + 2> e = sring[(shead + lane) & (kRing - 1)];
+            const uint32_t dd = have ? e.draw : 0u;
+            const DrawDesc& D = d_draws[dd];
+            const ViewDesc V = d_views[D.view & kDrawViewMask];
+            const bool interior = (D.view & kDrawInterior) != 0;
+            const uint32_t dmesh = D.mesh;
+            auto fill_mesh = [&](IdEntry& x) { x.mesh = dmesh; };
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+                const bool rej = interior ? fast_reject_box(e.w[k], e.w[k + 1], e.w[k + 2], V, tiny_cull)
+                                          : fast_reject(e.w[k], e.w[k + 1], e.w[k + 2], V, tiny_cull);
+                if (have && rej) st.add(kStCulledTiny);
+                push(have && !rej, dd, e.tri + (uint32_t)k, fill_mesh);
+            }
+        }
     };
     for (uint64_t b = first + blockIdx.x; b < total; b += gridDim.x) {
         const WorkItem wi = locate_work(d_segs, n_segs, dpi, b);
@@ -720,12 +754,21 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                             if (all_out) st.add(kStCulledTiny, TPT);
                         }
                         const bool pass = any_valid && !all_out;
-                        if (__ballot(pass)) {
+                        const unsigned long long m = __ballot(pass);
+                        if (m) {
+                            if (pass) {
+                                StripEntry<TPT + 2>& se = sring[(stail + rank_in(m)) & (kRing - 1)];
 #pragma unroll
-                            for (int k = 0; k < TPT; ++k) {
-                                const bool rej = reject(tag, w[k], w[k + 1], w[k + 2], V);
-                                if (pass && rej) st.add(kStCulledTiny);
-                                push(pass && !rej, d, tri[k], fill_id);
+                                for (int i = 0; i < TPT + 2; ++i) se.w[i] = w[i];
+                                se.draw = d;
+                                se.tri = tri[0];
+                            }
+                            stail += (uint32_t)__popcll(m);
+                            if (stail - shead >= 64) {
+                                wave_lds_sync();
+                                drain_strips(64);
+                                shead += 64;
+                                wave_lds_sync();
                             }
                         }
                     };
@@ -824,6 +867,13 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                 if (D.view & kDrawInterior) body(std::true_type{});
                 else body(std::false_type{});
             }
+        }
+    }
+    if constexpr (STRIPS) {
+        if (stail != shead) {
+            wave_lds_sync();
+            drain_strips(stail - shead);
+            shead = stail;
         }
     }
     if (tail != head) {
