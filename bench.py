@@ -11,8 +11,11 @@ multi-view launch (C4: 64 views of uneven size, 513 meshes) against 64 per-view 
 resolve forward/backward ms (C5: 10M-triangle height field at 1024^2), and the CPU oracle timed on
 a bounded sample of C3 on this host.
 
+Each workload first runs the library's autotuner (curast_autotune) once, before the untimed
+warm-up; the chosen options are part of the JSON line (--no-autotune: library defaults).
+
   python bench.py [--steps K] [--warmup W] [--gpus 1] [--config c3|c2|c1] [--no-secondary]
-                  [--no-cpu-baseline] [--copy-probe]
+                  [--no-cpu-baseline] [--copy-probe] [--no-autotune]
 """
 import argparse
 import json
@@ -59,6 +62,19 @@ def split_meshes(api, scene, gm):
     return multi, single
 
 
+def autotuned_options(args, ctx, gm, views, outs) -> dict:
+    """Launch options from the library's autotuner (curast_autotune: coordinate descent over the
+    stage-1 kernel shape, thresholds and grid sizes, results unchanged), run once before the
+    untimed warm-up; {} with --no-autotune (library defaults)."""
+    if args.no_autotune:
+        return {}
+    t0 = time.time()
+    best = ctx.autotune(gm, views, outs)
+    tuned = {k: v for k, v in best.items() if v and k != "flags"}
+    log(f"[bench] autotuned in {time.time() - t0:.1f}s: {json.dumps(tuned)}")
+    return tuned
+
+
 def visible_tri_instances(api, ctx, scene, gm) -> int:
     """Triangle instances that survive the host cull (from the library's statistics)."""
     ctx.set_options(flags=api.FLAG_STATS)
@@ -78,8 +94,9 @@ def run_headline(args, api, torch, W):
     attrs = [m.attrs for m in gm]
     ctx = api.Context()
     vis_count, st = visible_tri_instances(api, ctx, scene, gm)
-    ctx.set_options(flags=api.FLAG_TIMING)
     vis = torch.empty((view.height, view.width), dtype=torch.int64, device="cuda")
+    tuned = autotuned_options(args, ctx, gm, [view], [vis])
+    ctx.set_options(**tuned, flags=api.FLAG_TIMING)
     out = torch.empty((view.height, view.width, 3), dtype=torch.float32, device="cuda")
 
     def step():
@@ -109,7 +126,8 @@ def run_headline(args, api, torch, W):
     tex = {} if args.no_secondary else run_textured(args, api, torch, W, ctx, gm, attrs, view, vis)
     return {"scene": scene, "gm": gm, "ctx": ctx, "vis": vis, "ms": ms, "stage_ms": stage_ms, "supersampling": ss,
             "compressed": cmp, "textured": tex,
-            "visible": vis_count, "stats": st, "multi": multi, "single": single, "options": ctx.options()}
+            "visible": vis_count, "stats": st, "multi": multi, "single": single, "options": ctx.options(),
+            "autotuned": bool(tuned)}
 
 
 def run_supersampling(args, api, torch, ctx, gm, attrs, view, ms_plain):
@@ -277,6 +295,8 @@ def run_batched(args, api, torch, W):
     ctx.rasterize_batched(gm, scene.views, outs)
     tri_views = ctx.stats()["tri_draws"]
     ctx.set_options(flags=0)
+    tuned = autotuned_options(args, ctx, gm, scene.views, outs)
+    ctx.set_options(**tuned)
     reps = max(2, args.steps // 4)
 
     def plain():
@@ -302,7 +322,7 @@ def run_batched(args, api, torch, W):
             "plain_ms": round(r["plain"], 3), "batched_ms": round(r["batched"], 3),
             "plain_gtris_s": round(tri_views / r["plain"] / 1e6, 3),
             "batched_gtris_s": round(tri_views / r["batched"] / 1e6, 3),
-            "batched_speedup": round(r["plain"] / r["batched"], 3)}
+            "batched_speedup": round(r["plain"] / r["batched"], 3), "autotuned": bool(tuned)}
 
 
 def run_resolve_bwd(args, api, torch, W):
@@ -388,6 +408,7 @@ def main():
     ap.add_argument("--no-secondary", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="library default options instead of autotuned ones")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
@@ -426,6 +447,8 @@ def main():
             "triangle_instances": int(scene.total_tri_instances),
             "triangle_instances_after_cull": int(h["visible"]),
             "frame": "clear + stages 1-3 + resolve (RGB)",
+            "options": ("autotuned: " if h["autotuned"] else "library defaults: ") +
+                       json.dumps({k: v for k, v in h["options"].items() if k != "flags"}),
         },
         "stage_ms": {k: round(v, 4) for k, v in h["stage_ms"].items()},
         "roofline": rl_main,

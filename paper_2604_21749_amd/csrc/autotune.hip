@@ -84,6 +84,11 @@ bool from_json(const std::string& line, const std::string& key, curast_options& 
     return true;
 }
 
+// A candidate is timed as the median of kTuneReps frames and replaces the best one only when at
+// least 2% faster (frame-to-frame noise on one box is about 1%).
+constexpr int kTuneReps = 5;
+constexpr float kTuneGain = 0.98f;
+
 float frame_ms(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* views, uint32_t n_views,
                hipStream_t s, int reps, int* rc)
 {
@@ -153,7 +158,7 @@ extern "C" int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint3
     best.flags = keep_flags & ~(0x8u | 0x20u);
     rc = curast_set_options(ctx, &best);
     if (rc) return rc;
-    float best_ms = frame_ms(ctx, meshes, M, views, n_views, s, 3, &rc);
+    float best_ms = frame_ms(ctx, meshes, M, views, n_views, s, kTuneReps, &rc);
     if (rc) return rc;
     // size the queues from the observed fill (twice the peak, at least 64K entries)
     uint64_t fill[3];
@@ -163,7 +168,7 @@ extern "C" int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint3
         best.q3_capacity = std::max<uint32_t>(1u << 16, pow2_at_least(2 * fill[2] + 1));
         rc = curast_set_options(ctx, &best);
         if (rc) return rc;
-        best_ms = frame_ms(ctx, meshes, M, views, n_views, s, 3, &rc);
+        best_ms = frame_ms(ctx, meshes, M, views, n_views, s, kTuneReps, &rc);
         if (rc) return rc;
     }
     uint64_t max_draws = 0;
@@ -196,8 +201,8 @@ extern "C" int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint3
                 cand.*(ax.ptr) = v;
                 if (curast_set_options(ctx, &cand) != CURAST_OK) continue;
                 int r2 = 0;
-                const float ms = frame_ms(ctx, meshes, M, views, n_views, s, 3, &r2);
-                if (r2 == CURAST_OK && ms < 0.97f * best_ms) {
+                const float ms = frame_ms(ctx, meshes, M, views, n_views, s, kTuneReps, &r2);
+                if (r2 == CURAST_OK && ms < kTuneGain * best_ms) {
                     best = cand;
                     best_ms = ms;
                     improved = true;
