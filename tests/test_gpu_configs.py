@@ -93,6 +93,13 @@ def test_c4_batched_graph_matches_plain_and_oracle():
         for i in (0, 17, 63):
             ref_plain = api.as_uint64(c.rasterize_meshes(gm, moved[i]))
             assert_vis_equal(api.as_uint64(outs[i]), ref_plain, f"C4 moved view {i}")
+        # the options the autotuner picks for the batched frame (what the benchmark times)
+        tuned = c.autotune(gm, views, outs)
+        print(f"[c4] autotuned options {tuned}", flush=True)
+        c.rasterize_batched(gm, views, outs)
+        torch.cuda.synchronize()
+        for i, o in enumerate(outs):
+            assert_vis_equal(api.as_uint64(o), plain_h[i], f"C4 autotuned view {i}")
     for i in (0, 31):
         ref = O.rasterize(s.meshes, views[i], threads=oracle_threads())
         assert_vis_equal(plain_h[i], ref, f"C4 view {i} vs oracle")
