@@ -32,7 +32,7 @@ def declared_functions():
     return sorted(set(re.findall(r"\b(curast_\w+)\s*\(", text)))
 
 
-def test_header_declares_the_north_star_calls():
+def test_header_declares_the_boundary_calls():
     names = declared_functions()
     for n in ("curast_create", "curast_rasterize", "curast_resolve", "curast_resolve_backward"):
         assert n in names

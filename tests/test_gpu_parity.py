@@ -130,7 +130,7 @@ def test_instanced_stage1_modes(mode, tpt):
             assert_vis_equal(api.as_uint64(vis), O.rasterize(s.meshes, s.views[0]), f"instanced seed {seed} mode {mode}")
 
 
-def test_north_star_entry_point_matches_mesh_list(ctx):
+def test_single_mesh_entry_point_matches_mesh_list(ctx):
     s = W.scene_c1()
     m = s.meshes[0]
     g = api.GpuMesh.from_host(m)
