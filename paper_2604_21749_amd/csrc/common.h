@@ -159,11 +159,14 @@ struct ResolveArgs {
     const unsigned long long* vis;
     int32_t W, H;
     float hW, hH;
-    const uint64_t* bases;        // [n_pairs + 1] exclusive prefix of triangle counts
+    const uint64_t* bases;        // [n_meshes + 1] first global ID of each mesh (its instances follow
+                                  // one another, T IDs apart); the last entry is the ID count
+    const uint32_t* mesh_pair;    // [n_meshes] index of each mesh's first (mesh, instance) pair
     const DrawDesc* pairs;        // [n_pairs] draw matrix of every (mesh, instance) for this view
     const MeshDesc* meshes;
     const float* const* attrs;    // [M] per-mesh attribute pointers
     uint32_t n_pairs;
+    uint32_t n_meshes;
     uint32_t C;
     float* out;                   // [H][W][C], or [H/ss][W/ss][C] when supersampled
     uint32_t ss;                  // samples per axis and output pixel (1: no supersampling)

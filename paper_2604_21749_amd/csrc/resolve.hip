@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) project_kernel(ProjectArgs a)
 // ----------------------------------------------------------------------------------------------
 // Resolve of a multi-mesh, multi-instance visibility buffer
 // ----------------------------------------------------------------------------------------------
-constexpr uint32_t kLdsBases = 2048;   // prefix entries staged in LDS for the binary search
+constexpr uint32_t kLdsBases = 2048;   // per-mesh first IDs staged in LDS for the binary search
 
 // The triangle of pixel p of the view (row-major index) and its interpolation weights there;
 // false for an empty pixel or an invalid triangle.
@@ -94,19 +94,24 @@ __device__ __forceinline__ bool pixel_triangle(const ResolveArgs& a, const uint6
                                                const MeshDesc* __restrict__ meshes, uint64_t p, uint32_t& pair,
                                                uint32_t (&vi)[3])
 {
-    const uint32_t np = a.n_pairs;
+    // the int64 prefix of triangle counts over (mesh, instance) pairs (Sec. 4.4) is searched at
+    // mesh granularity: the instances of mesh m hold IDs B[m] + i T_m .. B[m] + (i + 1) T_m - 1,
+    // so the instance is one exact integer division (the last mesh with B[m] <= id has T_m > 0)
+    const uint32_t nm = a.n_meshes;
     const unsigned long long key = gl(a.vis)[p];
     const uint64_t id = key & kIdMask;
-    if (key == kEmptyKey || id >= B[np]) return false;
-    uint32_t lo = 0, hi = np;
+    if (key == kEmptyKey || id >= B[nm]) return false;
+    uint32_t lo = 0, hi = nm;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
         if (B[mid] <= id) lo = mid;
         else hi = mid;
     }
-    const MeshDesc& M = meshes[pairs[lo].mesh];
-    mesh_triangle(M, id - B[lo], vi);
-    pair = lo;
+    const MeshDesc& M = meshes[lo];
+    const uint64_t off = id - B[lo];
+    const uint64_t inst = off >= M.T ? off / M.T : 0;
+    mesh_triangle(M, off - inst * M.T, vi);
+    pair = a.mesh_pair[lo] + (uint32_t)inst;
     return vi[0] < M.V && vi[1] < M.V && vi[2] < M.V;
 }
 
@@ -145,9 +150,9 @@ __device__ __forceinline__ bool resolve_hit(const ResolveArgs& a, const uint64_t
 __device__ __forceinline__ const uint64_t* stage_bases(const ResolveArgs& a, const uint64_t* __restrict__ bases,
                                                        uint64_t* s_bases)
 {
-    const bool staged = a.n_pairs <= kLdsBases;
+    const bool staged = a.n_meshes <= kLdsBases;
     if (staged) {
-        for (uint32_t i = threadIdx.x; i <= a.n_pairs; i += blockDim.x) s_bases[i] = bases[i];
+        for (uint32_t i = threadIdx.x; i <= a.n_meshes; i += blockDim.x) s_bases[i] = bases[i];
         __syncthreads();
     }
     return staged ? s_bases : bases;

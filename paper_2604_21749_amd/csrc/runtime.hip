@@ -791,7 +791,8 @@ int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, c
     for (uint32_t m = 0; m < M; ++m) np += n_inst(meshes[m]);
     if (np > 0xFFFFFFF0ull) return fail(ctx, CURAST_E_INVALID, "too many (mesh, instance) pairs");
     const size_t off_bases = 0;
-    const size_t off_pairs = align_up(sizeof(uint64_t) * (np + 1), 256);
+    const size_t off_mpair = align_up(sizeof(uint64_t) * ((size_t)M + 1), 256);
+    const size_t off_pairs = align_up(off_mpair + sizeof(uint32_t) * std::max<uint32_t>(M, 1), 256);
     const size_t off_meshes = align_up(off_pairs + sizeof(DrawDesc) * std::max<uint64_t>(np, 1), 256);
     const size_t off_attrs = align_up(off_meshes + sizeof(MeshDesc) * std::max<uint32_t>(M, 1), 256);
     const size_t off_tex = align_up(off_attrs + sizeof(float*) * std::max<uint32_t>(M, 1), 256);
@@ -800,6 +801,7 @@ int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, c
     if (rc) return rc;
     char* h = static_cast<char*>(ctx->resolve_stage.host);
     uint64_t* bases = reinterpret_cast<uint64_t*>(h + off_bases);
+    uint32_t* mpair = reinterpret_cast<uint32_t*>(h + off_mpair);
     DrawDesc* pairs = reinterpret_cast<DrawDesc*>(h + off_pairs);
     MeshDesc* md = reinterpret_cast<MeshDesc*>(h + off_meshes);
     const float** ap = reinterpret_cast<const float**>(h + off_attrs);
@@ -808,6 +810,8 @@ int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, c
     for (uint32_t m = 0; m < M; ++m) {
         md[m] = mesh_desc(meshes[m]);
         ap[m] = attrs[m];
+        bases[m] = base;
+        mpair[m] = (uint32_t)p;
         if (textures) {
             TexDesc t{};
             t.texels = textures[m].texels;
@@ -822,7 +826,6 @@ int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, c
             td[m] = t;
         }
         for (uint32_t i = 0; i < n_inst(meshes[m]); ++i, ++p) {
-            bases[p] = base;
             draw_matrix(view.view_proj, meshes[m].instances ? meshes[m].instances + 12ull * i : nullptr, pairs[p].A);
             pairs[p].id_base = base;
             pairs[p].view = 0;
@@ -830,7 +833,7 @@ int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, c
             base += meshes[m].num_triangles;
         }
     }
-    bases[np] = base;
+    bases[M] = base;
     char* d = static_cast<char*>(ctx->resolve_stage.dev);
     a.vis = reinterpret_cast<const unsigned long long*>(view.visbuffer);
     a.W = view.width;
@@ -838,11 +841,13 @@ int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, c
     a.hW = 0.5f * (float)view.width;
     a.hH = 0.5f * (float)view.height;
     a.bases = reinterpret_cast<const uint64_t*>(d + off_bases);
+    a.mesh_pair = reinterpret_cast<const uint32_t*>(d + off_mpair);
     a.pairs = reinterpret_cast<const DrawDesc*>(d + off_pairs);
     a.meshes = reinterpret_cast<const MeshDesc*>(d + off_meshes);
     a.attrs = reinterpret_cast<const float* const*>(d + off_attrs);
     a.tex = textures ? reinterpret_cast<const TexDesc*>(d + off_tex) : nullptr;
     a.n_pairs = (uint32_t)np;
+    a.n_meshes = M;
     bytes_out = bytes;
     return CURAST_OK;
 }
