@@ -222,3 +222,19 @@ def test_strips_and_interior_draws(opts):
                 assert (visible == 2).sum() > 5, counts
             vis = c.rasterize_meshes(gm, s.views[0])
             assert_vis_equal(api.as_uint64(vis), O.rasterize(s.meshes, s.views[0]), f"strips seed {seed} {opts}")
+
+
+@pytest.mark.parametrize("opts", [dict(s1_block=96), dict(s1_tris_per_thread=3), dict(s1_multi_tris_per_thread=16),
+                                  dict(s1_mode=3, s1_multi_tris_per_thread=8), dict(s1_mode=4),
+                                  dict(s1_blocks_per_cu=65537), dict(small_px=65537),
+                                  dict(q2_capacity=(1 << 30) + 1)])
+def test_invalid_options_are_rejected(opts):
+    """curast_create / curast_set_options refuse options outside their documented ranges, and a
+    refused set_options leaves the context's options as they were."""
+    with pytest.raises(api.CurastError):
+        api.Context(**opts).close()
+    with api.Context() as c:
+        before = c.options()
+        with pytest.raises(api.CurastError):
+            c.set_options(**opts)
+        assert c.options() == before
