@@ -108,23 +108,33 @@ def run_headline(args, api, torch, W):
     torch.cuda.synchronize()
     ctx.reset_stage_times()
     torch.cuda.synchronize()
+    # per-frame HIP events on the launch stream (torch's current stream, which the binding passes)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t1 = time.perf_counter()
-    for _ in range(args.steps):
+    ev[0].record()
+    for i in range(args.steps):
         step()
+        ev[i + 1].record()
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ms = (t2 - t1) * 1000.0 / args.steps
+    per_frame = sorted(ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps))
+    frame_stats = {"mean_ms": round(sum(per_frame) / len(per_frame), 4),
+                   "median_ms": round(per_frame[len(per_frame) // 2], 4),
+                   "min_ms": round(per_frame[0], 4), "max_ms": round(per_frame[-1], 4)}
     times = ctx.stage_times()
     n = max(1, times["frames"])
     keys = ("clear", "stage1_multi", "stage1_single", "stage1_overflow", "stage2", "stage3", "resolve")
     stage_ms = {k: times[k] / n for k in keys}
     stage_ms["frame_gpu"] = sum(stage_ms.values())
-    log(f"[bench] {args.steps} frames: {ms:.3f} ms/frame wall, stages {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})}")
+    log(f"[bench] {args.steps} frames: {ms:.3f} ms/frame wall, events {json.dumps(frame_stats)}, "
+        f"stages {json.dumps({k: round(v, 4) for k, v in stage_ms.items()})}")
     multi, single = split_meshes(api, scene, gm)
     ss = {} if args.no_secondary else run_supersampling(args, api, torch, ctx, gm, attrs, view, ms)
     cmp = {} if args.no_secondary else run_compressed(args, api, torch, ctx, gm, attrs, view, vis_count)
     tex = {} if args.no_secondary else run_textured(args, api, torch, W, ctx, gm, attrs, view, vis)
     return {"scene": scene, "gm": gm, "ctx": ctx, "vis": vis, "ms": ms, "stage_ms": stage_ms, "supersampling": ss,
+            "frame_events": frame_stats,
             "compressed": cmp, "textured": tex,
             "visible": vis_count, "stats": st, "multi": multi, "single": single, "options": ctx.options(),
             "autotuned": bool(tuned)}
@@ -451,6 +461,7 @@ def main():
                        json.dumps({k: v for k, v in h["options"].items() if k != "flags"}),
         },
         "stage_ms": {k: round(v, 4) for k, v in h["stage_ms"].items()},
+        "frame_events_ms": h["frame_events"],
         "roofline": rl_main,
         "roofline_other_stage1_launch": rl_other,
         "gtris_s_submitted": round(scene.total_tri_instances / (h["ms"] * 1e-3) / 1e9, 4),
