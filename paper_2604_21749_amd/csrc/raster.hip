@@ -1434,17 +1434,12 @@ hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool
 template <int BLOCK, int TPT, bool STRIPS>
 static hipError_t stage1_fast_dispatch(const RasterArgs& a, bool stats, uint32_t grid, hipStream_t s)
 {
+    // the statistics variants (a measurement aid) decide per mesh, which is right for any launch
     const bool any = (a.compressed_parts >> a.part) & 1u, all = (a.compressed_parts >> (a.part + 8)) & 1u;
-    if (all) {
-        if (stats) stage1_fast_kernel<BLOCK, TPT, STRIPS, true, 1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
-        else stage1_fast_kernel<BLOCK, TPT, STRIPS, false, 1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
-    } else if (any) {
-        if (stats) stage1_fast_kernel<BLOCK, TPT, STRIPS, true, -1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
-        else stage1_fast_kernel<BLOCK, TPT, STRIPS, false, -1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
-    } else {
-        if (stats) stage1_fast_kernel<BLOCK, TPT, STRIPS, true, 0><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
-        else stage1_fast_kernel<BLOCK, TPT, STRIPS, false, 0><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
-    }
+    if (stats) stage1_fast_kernel<BLOCK, TPT, STRIPS, true, -1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    else if (all) stage1_fast_kernel<BLOCK, TPT, STRIPS, false, 1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    else if (any) stage1_fast_kernel<BLOCK, TPT, STRIPS, false, -1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    else stage1_fast_kernel<BLOCK, TPT, STRIPS, false, 0><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
     return hipGetLastError();
 }
 
