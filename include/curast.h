@@ -356,6 +356,8 @@ int curast_resolve_backward(curast_ctx* ctx, const uint64_t* visbuffer, int32_t 
  * The chosen options are applied to ctx, returned in `chosen` (may be NULL) and, when
  * cache_path is not NULL, stored in a JSON file keyed by device and scene class; an existing
  * entry for the same key is loaded instead of measuring.  views' visbuffers are overwritten.
+ * Candidates are timed with the context's stage timers (GPU time of the frame's kernels), which
+ * are reset.
  */
 int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* views,
                     uint32_t n_views, const char* cache_path, curast_options* chosen, void* stream);

@@ -84,8 +84,9 @@ bool from_json(const std::string& line, const std::string& key, curast_options& 
     return true;
 }
 
-// A candidate is timed as the median of kTuneReps frames and replaces the best one only when at
-// least 2% faster (frame-to-frame noise on one box is about 1%).
+// A candidate is timed on the GPU only (the library's frame events, from the first kernel of a
+// frame to its last, so host planning jitter stays out), as the mean of kTuneReps frames after
+// one warm-up frame, and replaces the best one only when at least 2% faster.
 constexpr int kTuneReps = 5;
 constexpr float kTuneGain = 0.98f;
 
@@ -96,26 +97,25 @@ float frame_ms(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const cur
         return n_views == 1 ? curast_rasterize_meshes(ctx, meshes, M, views, s)
                             : curast_rasterize_batched(ctx, meshes, M, views, n_views, s);
     };
-    *rc = run();   // warm-up (and graph capture)
+    curast_options o{};
+    *rc = curast_get_options(ctx, &o);
     if (*rc) return 1e30f;
-    hipEvent_t a, b;
-    hipEventCreate(&a);
-    hipEventCreate(&b);
-    std::vector<float> t;
-    for (int i = 0; i < reps && *rc == 0; ++i) {
-        hipEventRecord(a, s);
-        *rc = run();
-        hipEventRecord(b, s);
-        hipEventSynchronize(b);
-        float ms = 0.0f;
-        hipEventElapsedTime(&ms, a, b);
-        t.push_back(ms);
-    }
-    hipEventDestroy(a);
-    hipEventDestroy(b);
-    if (*rc || t.empty()) return 1e30f;
-    std::sort(t.begin(), t.end());
-    return t[t.size() / 2];
+    const uint32_t flags = o.flags;
+    o.flags |= CURAST_FLAG_TIMING;
+    *rc = curast_set_options(ctx, &o);
+    if (*rc) return 1e30f;
+    *rc = run();   // warm-up (and graph capture)
+    if (*rc == 0) *rc = curast_reset_stage_times(ctx);
+    for (int i = 0; i < reps && *rc == 0; ++i) *rc = run();
+    if (*rc == 0) *rc = hipStreamSynchronize(s) == hipSuccess ? CURAST_OK : CURAST_E_HIP;
+    double ms[9] = {};
+    uint64_t frames = 0;
+    if (*rc == 0) *rc = curast_get_stage_times(ctx, ms, &frames);
+    o.flags = flags;
+    const int r2 = curast_set_options(ctx, &o);
+    if (*rc == 0) *rc = r2;
+    if (*rc || frames == 0) return 1e30f;
+    return (float)(ms[8] / (double)frames);
 }
 
 uint32_t pow2_at_least(uint64_t v)
@@ -195,6 +195,13 @@ extern "C" int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint3
     for (int pass = 0; pass < 2; ++pass) {
         bool improved = false;
         for (const Axis& ax : axes) {
+            // re-time the current best before each axis, so that one lucky measurement of it
+            // does not hide a real gain further on
+            if (curast_set_options(ctx, &best) == CURAST_OK) {
+                int r0 = 0;
+                const float again = frame_ms(ctx, meshes, M, views, n_views, s, kTuneReps, &r0);
+                if (r0 == CURAST_OK) best_ms = again;
+            }
             for (uint32_t v : ax.values) {
                 if (best.*(ax.ptr) == v) continue;
                 curast_options cand = best;
