@@ -46,7 +46,6 @@ def lib():
             "orc_id_bases": [P, C.c_uint32, P],
             "orc_decode_id": [P, C.c_uint32, P, C.c_int64, P, P, P],
             "orc_rasterize": [P, C.c_uint32, P, P, C.c_int],
-            "orc_rasterize_masked": [P, C.c_uint32, P, P, P, C.c_int],
             "orc_rasterize_range": [P, C.c_uint32, P, C.c_int64, C.c_int64, C.c_uint64, C.c_uint64, P, C.c_int],
             "orc_coverage_counts": [P, C.c_uint32, P, P, P],
             "orc_rasterize_brute": [P, C.c_uint32, P, P],
@@ -123,15 +122,6 @@ def rasterize(meshes, view, threads: int = 0) -> np.ndarray:
     pk = _Pack(meshes, view)
     vis = np.empty((view.height, view.width), np.uint64)
     _check(lib().orc_rasterize(pk.meshes, pk.M, C.byref(pk.view), vis.ctypes.data, threads), "rasterize")
-    return vis
-
-
-def rasterize_masked(meshes, view, mask: np.ndarray, threads: int = 0) -> np.ndarray:
-    pk = _Pack(meshes, view)
-    mask = np.ascontiguousarray(mask, np.uint8)
-    vis = np.empty((view.height, view.width), np.uint64)
-    _check(lib().orc_rasterize_masked(pk.meshes, pk.M, C.byref(pk.view), mask.ctypes.data, vis.ctypes.data,
-                                      threads), "rasterize_masked")
     return vis
 
 

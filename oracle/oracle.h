@@ -80,10 +80,6 @@ int orc_decode_id(const orc_mesh* meshes, uint32_t M, const int64_t* bases, int6
    are split over threads, each with a private buffer, merged by elementwise minimum. */
 int orc_rasterize(const orc_mesh* meshes, uint32_t M, const orc_view* view, uint64_t* vis, int nthreads);
 
-/* Same result restricted to the pixels with mask[p] != 0 (others stay all ones). */
-int orc_rasterize_masked(const orc_mesh* meshes, uint32_t M, const orc_view* view,
-                         const uint8_t* mask, uint64_t* vis, int nthreads);
-
 /* Only the (mesh, instance) pairs in [pair_begin, pair_end) and triangles [tri_begin, tri_end)
    of each (used to time a bounded sample of a large workload). */
 int orc_rasterize_range(const orc_mesh* meshes, uint32_t M, const orc_view* view,

@@ -167,9 +167,8 @@ static uint64_t make_key(float depth, uint64_t id)
     return ((uint64_t)(bits >> 3) << 36) | (id & ID_MASK);
 }
 
-/* Rasterize one snapped triangle into vis (minimum), optionally restricted by mask. */
-static void raster_snapped(const svert v[3], uint64_t id, const vctx* vc, uint64_t* vis,
-                           const uint8_t* mask)
+/* Rasterize one snapped triangle into vis (minimum). */
+static void raster_snapped(const svert v[3], uint64_t id, const vctx* vc, uint64_t* vis)
 {
     int64_t area = (v[1].X - v[0].X) * (v[2].Y - v[0].Y) - (v[1].Y - v[0].Y) * (v[2].X - v[0].X);
     if (area <= 0) return;                                      /* back-facing or degenerate */
@@ -204,7 +203,6 @@ static void raster_snapped(const svert v[3], uint64_t id, const vctx* vc, uint64
         for (int64_t px = px0; px <= px1; ++px) {
             const int64_t Px = 256 * px + 128;
             const size_t p = (size_t)py * (size_t)vc->W + (size_t)px;
-            if (mask && !mask[p]) continue;
             int64_t E[3];
             int inside = 1;
             for (int k = 0; k < 3; ++k) {
@@ -222,15 +220,14 @@ static void raster_snapped(const svert v[3], uint64_t id, const vctx* vc, uint64
 }
 
 /* Full per-triangle definition: near rejection, clipping, fan, snapping, rasterization. */
-static void raster_triangle(const cvert c[3], uint64_t id, const vctx* vc, uint64_t* vis,
-                            const uint8_t* mask)
+static void raster_triangle(const cvert c[3], uint64_t id, const vctx* vc, uint64_t* vis)
 {
     if (c[0].w < vc->near_plane && c[1].w < vc->near_plane && c[2].w < vc->near_plane) return;
     if (!needs_clip(c, vc->near_plane)) {
         svert s[3];
         for (int k = 0; k < 3; ++k)
             if (!snap(c[k], vc, &s[k])) return;
-        raster_snapped(s, id, vc, vis, mask);
+        raster_snapped(s, id, vc, vis);
         return;
     }
     cvert poly[8];
@@ -241,7 +238,7 @@ static void raster_triangle(const cvert c[3], uint64_t id, const vctx* vc, uint6
         if (!snap(poly[k], vc, &sp[k])) return;
     for (int j = 1; j + 1 < n; ++j) {
         svert s[3] = {sp[0], sp[j], sp[j + 1]};
-        raster_snapped(s, id, vc, vis, mask);
+        raster_snapped(s, id, vc, vis);
     }
 }
 
@@ -311,7 +308,6 @@ typedef struct {
     const pair_t* pairs;
     int64_t npairs;
     const vctx* vc;
-    const uint8_t* mask;
     uint64_t w0, w1;
     uint64_t* vis;
 } job_t;
@@ -334,7 +330,7 @@ static void* worker(void* arg)
                 if (vi >= me->V) goto next;     /* out-of-range index: no fragments */
                 c[k] = transform(pr->A, me->pos + 3 * (uint64_t)vi);
             }
-            raster_triangle(c, (uint64_t)pr->base + t, j->vc, j->vis, j->mask);
+            raster_triangle(c, (uint64_t)pr->base + t, j->vc, j->vis);
         next:;
         }
     }
@@ -348,8 +344,7 @@ static int resolve_threads(int nthreads)
     return n > 0 ? (int)n : 1;
 }
 
-static int run(const orc_mesh* meshes, uint32_t M, const orc_view* view, const uint8_t* mask,
-               int64_t pb, int64_t pe, uint64_t tb, uint64_t te, uint64_t* vis, int nthreads)
+static int run(const orc_mesh* meshes, uint32_t M, const orc_view* view, int64_t pb, int64_t pe, uint64_t tb, uint64_t te, uint64_t* vis, int nthreads)
 {
     if (!view_ok(view) || !vis || (M && !meshes)) return -1;
     vctx vc = make_vctx(view);
@@ -392,7 +387,6 @@ static int run(const orc_mesh* meshes, uint32_t M, const orc_view* view, const u
         jobs[t].pairs = pairs;
         jobs[t].npairs = k;
         jobs[t].vc = &vc;
-        jobs[t].mask = mask;
         jobs[t].w0 = work * (uint64_t)t / (uint64_t)nt;
         jobs[t].w1 = work * (uint64_t)(t + 1) / (uint64_t)nt;
         if (t == 0) {
@@ -424,21 +418,14 @@ done:
 
 int orc_rasterize(const orc_mesh* meshes, uint32_t M, const orc_view* view, uint64_t* vis, int nthreads)
 {
-    return run(meshes, M, view, NULL, 0, INT64_MAX, 0, UINT64_MAX, vis, nthreads);
-}
-
-int orc_rasterize_masked(const orc_mesh* meshes, uint32_t M, const orc_view* view,
-                         const uint8_t* mask, uint64_t* vis, int nthreads)
-{
-    if (!mask) return -1;
-    return run(meshes, M, view, mask, 0, INT64_MAX, 0, UINT64_MAX, vis, nthreads);
+    return run(meshes, M, view, 0, INT64_MAX, 0, UINT64_MAX, vis, nthreads);
 }
 
 int orc_rasterize_range(const orc_mesh* meshes, uint32_t M, const orc_view* view,
                         int64_t pair_begin, int64_t pair_end, uint64_t tri_begin, uint64_t tri_end,
                         uint64_t* vis, int nthreads)
 {
-    return run(meshes, M, view, NULL, pair_begin, pair_end, tri_begin, tri_end, vis, nthreads);
+    return run(meshes, M, view, pair_begin, pair_end, tri_begin, tri_end, vis, nthreads);
 }
 
 /* ------------------------------------------------------------------------------------------ */

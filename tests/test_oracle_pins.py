@@ -734,3 +734,156 @@ def test_textured_resolve_near_plane_ground_vs_world_space_rays():
     lod = out[py, px, 0] * 255.0 / 20.0
     assert lod_ref.max() > 4.0 and lod_ref.min() < 2.0
     assert np.max(np.abs(lod - lod_ref)) < 2e-3
+
+
+# ----------------------------------------------------------------------------------------------
+# instance transforms, the one-mesh screen resolve and triangle ranges
+# ----------------------------------------------------------------------------------------------
+def _random_rigid_instances(rng, n, spread=1.5):
+    """Uniform random rotations times a scale in [0.5, 2] plus a translation (Sec. 4.5 instances:
+    row-major 3x4 object-to-world matrices [s R | t])."""
+    R = W.random_rotations(rng, n)
+    return W.instance_matrices(R, rng.uniform(0.5, 2.0, n), rng.uniform(-spread, spread, (n, 3)))
+
+
+def _fp64_window(pos, inst12, view):
+    """Closed form of the projection of an instanced vertex in fp64: clip = VP [X; 0 0 0 1] (v, 1),
+    sx = (x / w + 1) W / 2, sy likewise, plus the magnitude sums S_r = sum |VP_rj| |X_jc| |h_c| that
+    bound the binary32 rounding of each clip row."""
+    X = np.eye(4)
+    X[:3, :] = np.asarray(inst12, np.float64).reshape(3, 4)
+    vp = np.asarray(view.vp, np.float64).reshape(4, 4)
+    h = np.concatenate([np.asarray(pos, np.float64), np.ones((len(pos), 1))], 1)
+    clip = h @ (vp @ X).T
+    S = np.abs(h) @ (np.abs(vp) @ np.abs(X)).T
+    x, y, w = clip[:, 0], clip[:, 1], clip[:, 3]
+    return (x / w + 1.0) * view.width / 2, (y / w + 1.0) * view.height / 2, w, x, y, S
+
+
+def test_instanced_projection_matches_fp64_closed_form():
+    """orc_project of random rigid instances (rotation x scale + translation) against the fp64
+    product VP [X; 0 0 0 1] (v, 1).  The draw matrix rounds each entry after at most three
+    products and two sums, the vertex transform adds three roundings, so clip row r is within
+    7u S_r (u = 2^-24) of the fp64 value; the window position adds 1/w, x/w and the final fma.
+    A transposed or column-major reading of the 3x4 layout, a dropped translation, or the wrong
+    instance's matrix misses by orders of magnitude more."""
+    u = 2.0 ** -24
+    rng = np.random.default_rng(21)
+    for Wd, Hd in [(640, 480), (333, 517)]:
+        view = W.View(W.camera((0.4, 0.8, 6.0), (0.0, 0.0, 0.0), aspect=Wd / Hd), 0.01, Wd, Hd)
+        pos = rng.uniform(-1, 1, (300, 3)).astype(np.float32)
+        inst = _random_rigid_instances(rng, 24)
+        mesh = W.Mesh(pos, np.zeros((0, 3), np.uint32), inst=inst)
+        for i in range(inst.shape[0]):
+            got = O.project(mesh, view, instance=i).astype(np.float64)
+            ex, ey, ew, x, y, S = _fp64_window(pos, inst[i], view)
+            assert np.all(ew > 1.0)
+            dw = 7 * u * S[:, 3]
+            dx = 7 * u * S[:, 0]
+            dy = 7 * u * S[:, 1]
+            tol_x = 2 * ((Wd / 2) * (dx / ew + np.abs(x) * dw / ew ** 2 + 3 * u * np.abs(x / ew)) + 2 * u * np.abs(ex))
+            tol_y = 2 * ((Hd / 2) * (dy / ew + np.abs(y) * dw / ew ** 2 + 3 * u * np.abs(y / ew)) + 2 * u * np.abs(ey))
+            assert np.all(np.abs(got[:, 0] - ex) <= tol_x), (Wd, i, np.max(np.abs(got[:, 0] - ex) / tol_x))
+            assert np.all(np.abs(got[:, 1] - ey) <= tol_y), (Wd, i, np.max(np.abs(got[:, 1] - ey) / tol_y))
+            assert np.all(np.abs(got[:, 2] - ew) <= 2 * dw), (Wd, i)
+            # the bound is tight enough to matter: the errors are well above zero on some vertices
+            assert np.max(tol_x) < 1e-3 * Wd
+
+
+def test_instanced_rasterization_matches_pretransformed_meshes():
+    """Rasterizing a mesh under instance matrices X_i against rasterizing copies of the mesh
+    transformed on the host.  (1) Diagonal power-of-two scales with signs: X v is exact in
+    binary32 and every product A_rc v_c equals VP_rc (X v)_c exactly, so both buffers must be
+    identical bit for bit (IDs agree because instance i of one mesh and mesh i of the copies have
+    the same base i T).  (2) General rigid instances (host transform in fp64, rounded to binary32):
+    the buffers differ only where a pixel centre lies within rounding of an edge or where depths
+    tie, so nearly every covered pixel holds the same triangle of the same instance."""
+    rng = np.random.default_rng(22)
+    s = W.random_tiny_scene(31, n_tris=40, width=96, height=72, spread=1.2)
+    base = s.meshes[0]
+    view = s.views[0]
+    # shift the mesh so that its object-space origin is at its centre (instances then stay in view)
+    centre = base.pos.astype(np.float64).mean(0)
+    pos0 = (base.pos.astype(np.float64) - centre).astype(np.float32)
+    signs = [(1, 1, 1), (-1, 1, 1), (1, -1, 1), (1, 1, -1), (-1, -1, 1)]
+    diag = []
+    for k, sg in enumerate(signs):
+        sc = [sg[0] * 2.0 ** rng.integers(-1, 2), sg[1] * 2.0 ** rng.integers(-1, 2), sg[2] * 1.0]
+        m = np.zeros((3, 4), np.float32)
+        m[0, 0], m[1, 1], m[2, 2] = sc
+        diag.append(m.reshape(12))
+    diag = np.array(diag, np.float32)
+    # translation 0 keeps column 3 of the draw matrix equal to VP's; the camera looks at the origin
+    view_o = W.View(W.camera((0.0, 0.0, 3.0), (0.0, 0.0, 0.0), aspect=view.width / view.height), 0.01,
+                    view.width, view.height)
+    inst_mesh = W.Mesh(pos0, base.idx, inst=diag)
+    copies = [W.Mesh((pos0 * np.array([d[0], d[5], d[10]], np.float32)).astype(np.float32), base.idx) for d in diag]
+    a = O.rasterize([inst_mesh], view_o, threads=2)
+    b = O.rasterize(copies, view_o, threads=2)
+    assert (a != O.EMPTY).sum() > 500
+    assert np.array_equal(a, b)
+    # general rigid instances
+    inst = _random_rigid_instances(rng, 6, spread=0.4)
+    inst_mesh = W.Mesh(pos0, base.idx, inst=inst)
+    h = np.concatenate([pos0.astype(np.float64), np.ones((len(pos0), 1))], 1)
+    copies = [W.Mesh((h @ inst[i].astype(np.float64).reshape(3, 4).T).astype(np.float32), base.idx)
+              for i in range(inst.shape[0])]
+    a = O.rasterize([inst_mesh], view_o, threads=2)
+    b = O.rasterize(copies, view_o, threads=2)
+    cov = (a != O.EMPTY) | (b != O.EMPTY)
+    assert cov.sum() > 1000
+    same_id = (O.key_id(a) == O.key_id(b)) & (a != O.EMPTY) & (b != O.EMPTY)
+    assert same_id.sum() >= 0.97 * cov.sum(), same_id.sum() / cov.sum()
+
+
+def test_resolve_screen_equals_resolve_per_mesh_instance():
+    """orc_resolve_screen of one (mesh, instance) from orc_project's positions equals orc_resolve
+    of the whole scene bit for bit on that pair's pixels (same binary32 steps), and is 0 on every
+    other pixel (other meshes, other instances, empty).  orc_resolve itself is pinned by the
+    constant-attribute and world-space ray-hit tests above."""
+    a = W.random_tiny_scene(41, n_tris=30, n_instances=3, spread=2.5, width=64, height=48)
+    b = W.random_tiny_scene(42, n_tris=25, near_crossing=True, width=64, height=48)
+    meshes = [a.meshes[0], b.meshes[0]]
+    view = a.views[0]
+    vis = O.rasterize(meshes, view)
+    full = O.resolve(meshes, view, vis, [m.attrs for m in meshes])
+    bases = O.id_bases(meshes)
+    ids = O.key_id(vis).astype(np.int64)
+    cov = vis != O.EMPTY
+    pairs = [(0, i) for i in range(3)] + [(1, 0)]
+    seen = np.zeros(vis.shape, bool)
+    for p, (m, i) in enumerate(pairs):
+        mesh = meshes[m]
+        pss = O.project(mesh, view, instance=i)
+        out = O.resolve_screen(vis, mesh.idx, int(bases[p]), pss, mesh.attrs)
+        mine = cov & (ids >= bases[p]) & (ids < bases[p] + mesh.num_triangles)
+        assert mine.sum() > 20, (m, i)
+        assert np.array_equal(out[mine], full[mine]), (m, i)
+        assert np.all(out[~mine] == 0), (m, i)
+        seen |= mine
+    assert np.array_equal(seen, cov)
+
+
+def test_rasterize_range_splits_and_full_range():
+    """orc_rasterize_range (the CPU-baseline sampler): the full range equals orc_rasterize, an
+    empty range leaves every pixel empty, and the elementwise minimum over ranges that split the
+    pairs and the triangles at every index equals the full buffer (an off-by-one at a range end
+    drops or shifts a triangle)."""
+    s = W.random_tiny_scene(51, n_tris=18, n_instances=3, spread=1.0)
+    meshes, view = s.meshes, s.views[0]
+    full = O.rasterize(meshes, view, threads=2)
+    assert np.array_equal(O.rasterize_range(meshes, view, 0, 3, 0, 18, threads=2), full)
+    assert np.array_equal(O.rasterize_range(meshes, view, 0, 1 << 40, 0, 1 << 40, threads=3), full)
+    assert np.all(O.rasterize_range(meshes, view, 0, 3, 7, 7) == O.EMPTY)
+    assert np.all(O.rasterize_range(meshes, view, 2, 2, 0, 18) == O.EMPTY)
+    acc = np.full_like(full, O.EMPTY)
+    visible_parts = 0
+    for p in range(3):
+        for t in range(18):
+            part = O.rasterize_range(meshes, view, p, p + 1, t, t + 1)
+            ids = O.key_id(part[part != O.EMPTY]).astype(np.int64)
+            assert np.all(ids == p * 18 + t)
+            visible_parts += int(ids.size > 0)
+            acc = np.minimum(acc, part)
+    assert visible_parts >= 20
+    assert np.array_equal(acc, full)
