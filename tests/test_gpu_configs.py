@@ -2,8 +2,9 @@
 
 C2 and C3 compare the whole visibility buffer with the full oracle (C3: 9.1G triangle instances,
 about a minute of CPU time on 16 cores).  C4 checks the batched graph launch view by view against
-plain launches (every view) and the oracle (sampled views), over several graph replays.  C5
-checks the differentiable resolve: forward, fp64 reference gradients and central differences.
+plain launches over several graph replays, and every view against the oracle.  C5 checks the
+differentiable resolve: forward, fp64 reference gradients under an upstream gradient formed from
+oracle values only, the autograd wrapper, and central differences.
 """
 import numpy as np
 import pytest
@@ -100,53 +101,88 @@ def test_c4_batched_graph_matches_plain_and_oracle():
         torch.cuda.synchronize()
         for i, o in enumerate(outs):
             assert_vis_equal(api.as_uint64(o), plain_h[i], f"C4 autotuned view {i}")
-    for i in (0, 31):
-        ref = O.rasterize(s.meshes, views[i], threads=oracle_threads())
-        assert_vis_equal(plain_h[i], ref, f"C4 view {i} vs oracle")
+    # every view against the oracle (the batched frames equal these view by view, above)
+    for i, v in enumerate(views):
+        ref = O.rasterize(s.meshes, v, threads=oracle_threads())
+        assert_vis_equal(plain_h[i], ref, f"C4 view {i} ({v.width}x{v.height}) vs oracle")
 
 
-def test_c5_resolve_forward_and_backward():
+def _c5_oracle():
+    """C5 from the oracle alone: visibility buffer, screen positions, fp32 image and the upstream
+    gradient of L = sum over covered pixels of (out - target)^2, g = 2 (out - target) formed in
+    fp32 from the oracle's fp32 image (0 on empty pixels)."""
     s = W.scene_c5()
     m = s.meshes[0]
     view = s.views[0]
-    target = s.meta["target"]
+    vis = O.rasterize([m], view, threads=oracle_threads())
+    pss = O.project(m, view)
+    out = O.resolve_screen(vis, m.idx, 0, pss, m.attrs)
+    cov = vis != O.EMPTY
+    g = np.where(cov[..., None], np.float32(2.0) * (out - s.meta["target"].astype(np.float32)),
+                 np.float32(0.0)).astype(np.float32)
+    return s, m, view, vis, pss, out, g
+
+
+def _assert_grad_close(got, ref, what):
+    """|got - ref| <= 1e-3 max(|ref|, 1e-3 rms(ref)) element by element (acceptance of the
+    differentiable resolve)."""
+    scale = np.maximum(np.abs(ref), 1e-3 * np.sqrt(np.mean(ref ** 2)))
+    rel = np.abs(got - ref) / scale
+    assert np.all(rel <= 1e-3), f"{what}: worst relative error {rel.max()}"
+
+
+def test_c5_resolve_forward_and_backward():
+    """Forward (visibility, screen positions, resolve) against the oracle; the backward kernel
+    called through the C ABI on inputs that all come from the oracle (visibility buffer, screen
+    positions, attributes, upstream gradient) against the fp64 reference gradients under the
+    same upstream gradient; position gradients against central differences of the L2 loss."""
+    s, m, view, ref_vis, pss_ref, out_ref, g = _c5_oracle()
     with api.Context() as c:
-        g = api.GpuMesh.from_host(m)
-        vis = c.rasterize_meshes([g], view)
-        pos_ss = c.project(g, view)
-        out = c.resolve_screen(vis, g.idx, pos_ss, g.attrs)
+        gmesh = api.GpuMesh.from_host(m)
+        vis = c.rasterize_meshes([gmesh], view)
+        pos_ss = c.project(gmesh, view)
+        out = c.resolve_screen(vis, gmesh.idx, pos_ss, gmesh.attrs)
         torch.cuda.synchronize()
-        vis_h = api.as_uint64(vis)
-        pss_h = pos_ss.cpu().numpy()
-        # autograd wrapper: L = sum (out - target)^2 restricted to covered pixels
-        attrs = g.attrs.clone().requires_grad_(True)
-        pss = pos_ss.clone().requires_grad_(True)
-        img = api.ResolveFn.apply(attrs, pss, vis, g.idx, 0, c)
-        tgt = torch.from_numpy(target).cuda()
-        covered = (vis != -1).unsqueeze(-1)
-        loss = torch.where(covered, (img - tgt) ** 2, torch.zeros_like(img)).sum()
-        loss.backward()
-        ga = attrs.grad.cpu().numpy().astype(np.float64)
-        gp = pss.grad.cpu().numpy().astype(np.float64)
-        out_h = out.cpu().numpy()
-    ref_vis = O.rasterize([m], view, threads=oracle_threads())
-    assert_vis_equal(vis_h, ref_vis, "C5")
-    assert np.array_equal(pss_h, O.project(m, view)), "screen positions differ from the oracle"
-    assert_resolve_close(out_h, O.resolve_screen(ref_vis, m.idx, 0, pss_h, m.attrs), "C5 resolve")
-    # fp64 reference gradients under the upstream gradient autograd handed to the kernel:
-    # d/d img of sum (img - target)^2 on covered pixels = 2 (img - target), formed in fp32 from the
-    # fp32 image (an fp64 image would move g by ~1e-7 per pixel, which is not the kernel's error)
-    cov = ref_vis != O.EMPTY
-    g32 = np.where(cov[..., None], np.float32(2.0) * (out_h - target.astype(np.float32)), np.float32(0.0))
-    ra, rp = O.resolve_screen_backward_f64(ref_vis, m.idx, 0, pss_h, m.attrs, g32.astype(np.float64))
-    sa = np.maximum(np.abs(ra), 1e-3 * np.sqrt(np.mean(ra ** 2)))
-    assert np.all(np.abs(ga - ra) <= 1e-3 * sa), f"attribute gradient: {np.max(np.abs(ga - ra) / sa)}"
-    sp = np.maximum(np.abs(rp), 1e-3 * np.sqrt(np.mean(rp ** 2)))
-    assert np.all(np.abs(gp - rp) <= 1e-3 * sp), f"position gradient: {np.max(np.abs(gp - rp) / sp)}"
+        assert_vis_equal(api.as_uint64(vis), ref_vis, "C5")
+        assert np.array_equal(pos_ss.cpu().numpy(), pss_ref), "screen positions differ from the oracle"
+        assert_resolve_close(out.cpu().numpy(), out_ref, "C5 resolve")
+        # backward on oracle inputs only
+        vis_o = torch.from_numpy(ref_vis.view(np.int64)).cuda()
+        pss_o = torch.from_numpy(pss_ref).cuda()
+        g_o = torch.from_numpy(g).cuda()
+        ga = torch.zeros_like(gmesh.attrs)
+        gp = torch.zeros_like(pss_o)
+        c.resolve_backward(vis_o, gmesh.idx, pss_o, gmesh.attrs, g_o, ga, gp)
+        torch.cuda.synchronize()
+        ga = ga.cpu().numpy().astype(np.float64)
+        gp = gp.cpu().numpy().astype(np.float64)
+    ra, rp = O.resolve_screen_backward_f64(ref_vis, m.idx, 0, pss_ref, m.attrs, g.astype(np.float64))
+    _assert_grad_close(ga, ra, "attribute gradient")
+    _assert_grad_close(gp, rp, "position gradient")
     # central finite differences (eps 1e-3, fourth-order stencil) on 256 seeded visible vertices
+    cov = ref_vis != O.EMPTY
     used = np.unique(m.idx[O.key_id(ref_vis[cov]).astype(np.int64)])
     verts = np.random.default_rng(57).choice(used, 256, replace=False).astype(np.uint32)
-    fd = O.fd_pos_grad_l2(ref_vis, m.idx, 0, pss_h, m.attrs, target, verts, eps=1e-3, order4=True)
-    scale = np.maximum(np.abs(fd), 1e-3 * np.sqrt(np.mean(fd ** 2)))
-    rel = np.abs(gp[verts] - fd) / scale
-    assert np.all(rel <= 1e-3), f"FD check: worst relative error {rel.max()}"
+    fd = O.fd_pos_grad_l2(ref_vis, m.idx, 0, pss_ref, m.attrs, s.meta["target"], verts, eps=1e-3, order4=True)
+    _assert_grad_close(gp[verts], fd, "FD check")
+
+
+def test_c5_autograd_wrapper():
+    """ResolveFn (torch.autograd.Function) on the GPU's own forward: with L = sum(img * G) for the
+    oracle's upstream gradient G, autograd hands the backward exactly G, so its gradients must
+    match the fp64 reference gradients under G."""
+    s, m, view, ref_vis, pss_ref, out_ref, g = _c5_oracle()
+    with api.Context() as c:
+        gmesh = api.GpuMesh.from_host(m)
+        vis = c.rasterize_meshes([gmesh], view)
+        pos_ss = c.project(gmesh, view)
+        attrs = gmesh.attrs.clone().requires_grad_(True)
+        pss = pos_ss.clone().requires_grad_(True)
+        img = api.ResolveFn.apply(attrs, pss, vis, gmesh.idx, 0, c)
+        (img * torch.from_numpy(g).cuda()).sum().backward()
+        ga = attrs.grad.cpu().numpy().astype(np.float64)
+        gp = pss.grad.cpu().numpy().astype(np.float64)
+        assert_resolve_close(img.detach().cpu().numpy(), out_ref, "C5 autograd forward")
+    ra, rp = O.resolve_screen_backward_f64(ref_vis, m.idx, 0, pss_ref, m.attrs, g.astype(np.float64))
+    _assert_grad_close(ga, ra, "autograd attribute gradient")
+    _assert_grad_close(gp, rp, "autograd position gradient")

@@ -37,16 +37,22 @@ def test_no_meshes_clears_the_view(ctx):
 @pytest.mark.parametrize("graph", [True, False])
 def test_meshes_without_triangles_keep_the_id_bases(graph):
     """[empty, tiny instanced, empty x 3 instances, tiny, empty]: IDs skip nothing and the
-    resolve finds the right mesh."""
+    resolve finds the right mesh.  graph=True renders through curast_rasterize_batched (the
+    captured graph, replayed on the second frame) into two views; graph=False through
+    curast_rasterize_meshes (eager launches)."""
     a = W.random_tiny_scene(7, n_instances=3, n_tris=20, spread=3.0)
     b = W.random_tiny_scene(8, n_tris=12, near_crossing=True)
     meshes = [_empty_mesh(), a.meshes[0], _empty_mesh(3), b.meshes[0], _empty_mesh()]
     view = a.views[0]
-    flags = 0 if graph else api.FLAG_NO_GRAPH
-    with api.Context(flags=flags) as c:
+    second = W.View(b.views[0].vp, b.views[0].near, 31, 45)
+    with api.Context() as c:
         gm = [api.GpuMesh.from_host(m) for m in meshes]
-        for _ in range(2):     # the second frame replays the captured graph
-            vis = c.rasterize_meshes(gm, view)
+        for _ in range(2):     # with graph=True the second frame replays the captured graph
+            if graph:
+                vis, vis2 = c.rasterize_batched(gm, [view, second])
+                assert_vis_equal(api.as_uint64(vis2), O.rasterize(meshes, second), "second view")
+            else:
+                vis = c.rasterize_meshes(gm, view)
             ref = O.rasterize(meshes, view)
             assert_vis_equal(api.as_uint64(vis), ref, "meshes without triangles")
         out = c.resolve(gm, view, vis, [g.attrs for g in gm]).cpu().numpy()
