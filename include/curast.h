@@ -357,7 +357,10 @@ int curast_resolve_backward(curast_ctx* ctx, const uint64_t* visbuffer, int32_t 
  * cache_path is not NULL, stored in a JSON file keyed by device and scene class; an existing
  * entry for the same key is loaded instead of measuring.  views' visbuffers are overwritten.
  * Candidates are timed with the context's stage timers (GPU time of the frame's kernels), which
- * are reset.
+ * are reset.  Queue capacities are raised to twice the measured fill when that exceeds the
+ * library defaults and are never set below the defaults, so a cached choice does not push a
+ * busier scene of the same class into the in-place overflow path (q2_overflow / q3_overflow in
+ * curast_stats count triangles that took it).
  */
 int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* views,
                     uint32_t n_views, const char* cache_path, curast_options* chosen, void* stream);

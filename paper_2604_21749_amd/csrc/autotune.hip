@@ -15,6 +15,7 @@
 
 extern "C" int curast_internal_queue_counts(curast_ctx* ctx, uint64_t out[3]);
 extern "C" int curast_internal_num_cus(const curast_ctx* ctx);
+extern "C" int curast_internal_default_options(const curast_ctx* ctx, curast_options* out);
 
 namespace {
 
@@ -160,12 +161,17 @@ extern "C" int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint3
     if (rc) return rc;
     float best_ms = frame_ms(ctx, meshes, M, views, n_views, s, kTuneReps, &rc);
     if (rc) return rc;
-    // size the queues from the observed fill (twice the peak, at least 64K entries)
+    // grow the queues to twice the observed fill when that exceeds the library defaults; never
+    // shrink them below the defaults: the choice is cached for a whole scene class, and a scene of
+    // the class that forwards more triangles would otherwise fall back to the one-thread overflow
+    // pass (q2_overflow / q3_overflow in the statistics count such triangles)
     uint64_t fill[3];
-    if (curast_internal_queue_counts(ctx, fill) == CURAST_OK) {
-        best.q2_capacity = std::max<uint32_t>(1u << 16, pow2_at_least(2 * fill[0] + 1));
-        best.large_capacity = std::max<uint32_t>(1u << 14, pow2_at_least(2 * fill[1] + 1));
-        best.q3_capacity = std::max<uint32_t>(1u << 16, pow2_at_least(2 * fill[2] + 1));
+    curast_options defaults{};
+    if (curast_internal_queue_counts(ctx, fill) == CURAST_OK &&
+        curast_internal_default_options(ctx, &defaults) == CURAST_OK) {
+        best.q2_capacity = std::max<uint32_t>(defaults.q2_capacity, pow2_at_least(2 * fill[0] + 1));
+        best.large_capacity = std::max<uint32_t>(defaults.large_capacity, pow2_at_least(2 * fill[1] + 1));
+        best.q3_capacity = std::max<uint32_t>(defaults.q3_capacity, pow2_at_least(2 * fill[2] + 1));
         rc = curast_set_options(ctx, &best);
         if (rc) return rc;
         best_ms = frame_ms(ctx, meshes, M, views, n_views, s, kTuneReps, &rc);

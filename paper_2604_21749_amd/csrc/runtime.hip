@@ -70,7 +70,7 @@ struct Staging {
 };
 
 struct GraphEntry {
-    uint64_t key[10];
+    uint64_t key[11];
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -713,13 +713,16 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
     // graph path: one captured sequence per structure (sizes of the descriptor block, grid bound,
     // options); replays copy the new descriptor contents from the same pinned buffer
     const uint32_t grid1 = grid_for(P.max_batches);
-    uint64_t key[10] = {(uint64_t)M, (uint64_t)n_views, (uint64_t)P.max_bytes, (uint64_t)grid1,
+    // the queue capacities are kernel arguments of the captured launches, so they are part of the key
+    uint64_t key[11] = {(uint64_t)M, (uint64_t)n_views, (uint64_t)P.max_bytes, (uint64_t)grid1,
                        ((uint64_t)ctx->opt.s1_block << 32) | (ctx->opt.s1_tris_per_thread << 8) |
                            (ctx->opt.s1_multi_tris_per_thread << 4) | ctx->opt.s1_mode,
                        ((uint64_t)ctx->opt.s2_waves << 32) | ctx->opt.s3_blocks,
                        ((uint64_t)ctx->opt.flags << 32) | ctx->opt.small_px,
                        ((uint64_t)ctx->opt.medium_px << 32) | ctx->opt.s1_draws_per_item,
-                       ((uint64_t)P.compressed << 32) | P.compressed_parts, (uint64_t)ctx->opt.s1_blocks_per_cu};
+                       ((uint64_t)P.compressed << 32) | P.compressed_parts,
+                       ((uint64_t)ctx->opt.large_capacity << 32) | ctx->opt.s1_blocks_per_cu,
+                       ((uint64_t)ctx->opt.q2_capacity << 32) | ctx->opt.q3_capacity};
     GraphEntry* ge = nullptr;
     for (auto& g : ctx->graphs)
         if (std::memcmp(g.key, key, sizeof key) == 0) ge = &g;
@@ -1369,6 +1372,14 @@ int curast_internal_queue_counts(curast_ctx* ctx, uint64_t out[3])
 }
 
 int curast_internal_num_cus(const curast_ctx* ctx) { return ctx ? ctx->cus : 0; }
+
+// The library defaults on this context's device (internal, used by the autotuner).
+int curast_internal_default_options(const curast_ctx* ctx, curast_options* out)
+{
+    if (!ctx || !out) return CURAST_E_INVALID;
+    *out = resolve_defaults(curast_options{}, ctx->cus);
+    return CURAST_OK;
+}
 
 int64_t curast_id_bases(const curast_mesh* meshes, uint32_t M, int64_t* bases)
 {
