@@ -205,6 +205,28 @@ int curast_rasterize(curast_ctx* ctx, const float* vertices, uint32_t num_vertic
                      int32_t width, int32_t height, uint64_t* visbuffer, void* stream);
 
 /*
+ * Allocation-free form of curast_rasterize, for callers that cannot allocate memory: code under
+ * HIP stream capture, tight serving loops, harnesses that forbid hipMalloc.  Same arguments and
+ * the same visibility buffer as curast_rasterize; it calls no hipMalloc, hipFree, hipMemcpy or
+ * hipMemset, and on the host it allocates nothing either (except the message it stores when it
+ * returns an error).  The plan is built in fixed arrays, its
+ * descriptors go to the device as the argument of one small kernel, and descriptors, queues,
+ * counters and stage-3 bins live in a file-scope device array of about 17 MB per device (held
+ * until the process ends; its address is taken once per device by curast_create), instead of the
+ * context's buffers.  Its stage-2 queue holds 1M entries, its large-triangle store 64K records and
+ * its stage-3 queue 512K tile parts (the context's capacities when those are smaller); overflow
+ * falls back to in-place rasterization as in curast_rasterize, so results do not change.
+ * Limits: at most 32 instances (CURAST_E_INVALID beyond), views up to 16384 x 16384;
+ * CURAST_FLAG_STATS and CURAST_FLAG_TIMING are ignored.  All calls on one device share the one
+ * array and it keeps the last call's contents (the clear kernel zeroes the counters and bins each
+ * call needs): calls whose work overlaps on one device (other streams, other host threads) race.
+ */
+int curast_rasterize_noalloc(curast_ctx* ctx, const float* vertices, uint32_t num_vertices,
+                             const uint32_t* indices, uint64_t num_triangles, const float* instances,
+                             uint32_t num_instances, const float view_proj[16], float near_plane,
+                             int32_t width, int32_t height, uint64_t* visbuffer, void* stream);
+
+/*
  * Rasterize a list of meshes (Sec. 4: host-side mesh list with per-mesh/instance triangle-count
  * prefix sums) into one view.  meshes: host array of M descriptors.  Clears the view's buffer.
  */

@@ -85,6 +85,8 @@ SIGNATURES = {
     "curast_get_options": (C.c_int, [_P, C.POINTER(Options)]),
     "curast_rasterize": (C.c_int, [_P, _P, C.c_uint32, _P, C.c_uint64, _P, C.c_uint32, _P, C.c_float, C.c_int32,
                                    C.c_int32, _P, _P]),
+    "curast_rasterize_noalloc": (C.c_int, [_P, _P, C.c_uint32, _P, C.c_uint64, _P, C.c_uint32, _P, C.c_float,
+                                           C.c_int32, C.c_int32, _P, _P]),
     "curast_rasterize_meshes": (C.c_int, [_P, _P, C.c_uint32, _P, _P]),
     "curast_rasterize_batched": (C.c_int, [_P, _P, C.c_uint32, _P, C.c_uint32, _P]),
     "curast_project": (C.c_int, [_P, _P, C.c_uint32, _P, _P, _P]),
@@ -355,6 +357,23 @@ class Context:
         vp = np.ascontiguousarray(view_proj, np.float32).reshape(16)
         inst = None if instances is None else np.ascontiguousarray(instances, np.float32).reshape(-1, 12)
         self._check(lib().curast_rasterize(
+            self._h, vertices.data_ptr(), vertices.shape[0], indices.data_ptr(), indices.shape[0],
+            None if inst is None else inst.ctypes.data, 0 if inst is None else inst.shape[0], vp.ctypes.data,
+            float(near), int(width), int(height), out.data_ptr(), _stream(vertices.device)))
+        return out
+
+    def rasterize_noalloc(self, vertices: torch.Tensor, indices: torch.Tensor, view_proj, near: float, width: int,
+                          height: int, out: torch.Tensor, instances: Optional[np.ndarray] = None):
+        """curast_rasterize_noalloc: curast_rasterize through the library's static scratch (the
+        caller passes the output buffer; at most 32 instances)."""
+        _check_cuda(vertices, torch.float32, "vertices", 3)
+        _check_cuda(indices, torch.int32, "indices", 3)
+        _check_cuda(out, torch.int64, "out")
+        if tuple(out.shape) != (int(height), int(width)):
+            raise ValueError("out must have shape [height, width]")
+        vp = np.ascontiguousarray(view_proj, np.float32).reshape(16)
+        inst = None if instances is None else np.ascontiguousarray(instances, np.float32).reshape(-1, 12)
+        self._check(lib().curast_rasterize_noalloc(
             self._h, vertices.data_ptr(), vertices.shape[0], indices.data_ptr(), indices.shape[0],
             None if inst is None else inst.ctypes.data, 0 if inst is None else inst.shape[0], vp.ctypes.data,
             float(near), int(width), int(height), out.data_ptr(), _stream(vertices.device)))

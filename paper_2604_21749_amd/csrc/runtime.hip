@@ -15,6 +15,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -75,7 +76,7 @@ struct GraphEntry {
     hipGraphExec_t exec = nullptr;
 };
 
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 }  // namespace
 
@@ -103,6 +104,7 @@ struct curast_ctx {
     uint64_t timed_frames = 0;
     uint64_t draws_culled = 0;
     uint32_t* ranges = nullptr;   // [8] index range and bounding box of curast_compress_prepare
+    char* na_scratch = nullptr;   // this device's copy of the allocation-free form's scratch array
 };
 
 namespace {
@@ -434,12 +436,49 @@ MeshDesc mesh_desc(const curast_mesh& m)
     return d;
 }
 
-struct Plan {
+// Plan storage: heap vectors for the ordinary entry points, fixed arrays for the allocation-free
+// one (which takes one mesh, one view and at most kFixedDraws instances).
+template <class T>
+using HeapVec = std::vector<T>;
+
+constexpr size_t kFixedDraws = 32;
+
+template <class T, size_t N>
+struct FixedVec {
+    T buf[N];
+    size_t n = 0;
+    bool overflow = false;
+    void push_back(const T& v)
+    {
+        if (n < N) buf[n++] = v;
+        else overflow = true;
+    }
+    void resize(size_t k)
+    {
+        overflow |= k > N;
+        n = std::min(k, N);
+        for (size_t i = 0; i < n; ++i) buf[i] = T{};
+    }
+    size_t size() const { return n; }
+    bool empty() const { return n == 0; }
+    T* data() { return buf; }
+    const T* data() const { return buf; }
+    T& operator[](size_t i) { return buf[i]; }
+    const T& operator[](size_t i) const { return buf[i]; }
+    T& back() { return buf[n - 1]; }
+};
+
+template <class T>
+using FixVec = FixedVec<T, kFixedDraws>;
+
+template <template <class> class Vec>
+struct PlanT {
     FrameHeader hdr{};
-    std::vector<ViewDesc> views;
-    std::vector<MeshDesc> meshes;
-    std::vector<Segment> segs;
-    std::vector<DrawDesc> draws;
+    Vec<ViewDesc> views;
+    Vec<MeshDesc> meshes;
+    Vec<Segment> segs;
+    Vec<DrawDesc> draws;
+    Vec<uint32_t> mesh_draw_begin, mesh_draw_count;
     uint64_t tri_draws = 0;
     uint64_t draws_culled = 0;
     uint64_t total_pixels = 0;
@@ -449,10 +488,21 @@ struct Plan {
     uint32_t compressed_parts = 0;   // RasterArgs::compressed_parts of this frame's stage-1 parts
     size_t max_draws = 0;            // without any culling
     size_t off_views = 0, off_meshes = 0, off_segs = 0, off_draws = 0, bytes = 0, max_bytes = 0;
+    bool full() const;
 };
+template <>
+bool PlanT<HeapVec>::full() const { return false; }
+template <>
+bool PlanT<FixVec>::full() const
+{
+    return views.overflow || meshes.overflow || segs.overflow || draws.overflow || mesh_draw_begin.overflow ||
+           mesh_draw_count.overflow;
+}
+using Plan = PlanT<HeapVec>;
 
+template <template <class> class Vec>
 int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* meshes, uint32_t M,
-               const curast_view* views, uint32_t n_views, Plan& P, uint8_t* visible = nullptr)
+               const curast_view* views, uint32_t n_views, PlanT<Vec>& P, uint8_t* visible = nullptr)
 {
     if (M && !meshes) return fail(ctx, CURAST_E_INVALID, "meshes is NULL");
     if (!views || n_views == 0) return fail(ctx, CURAST_E_INVALID, "no view");
@@ -494,7 +544,11 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
     // triangles per work item of the first stage-1 launch (the vertex-sharing kernel runs 64-lane
     // workgroups)
     const uint32_t bt_multi = (o.s1_mode == 3 ? 64u : o.s1_block) * o.s1_multi_tris_per_thread;
-    std::vector<uint32_t> mesh_draw_begin(M), mesh_draw_count(M);
+    P.mesh_draw_begin.resize(M);
+    P.mesh_draw_count.resize(M);
+    if (P.full()) return fail(ctx, CURAST_E_INVALID, "too many meshes or views for the allocation-free form");
+    auto& mesh_draw_begin = P.mesh_draw_begin;
+    auto& mesh_draw_count = P.mesh_draw_count;
     for (uint32_t m = 0; m < M; ++m) {
         const curast_mesh& me = meshes[m];
         P.meshes[m] = mesh_desc(me);
@@ -537,6 +591,7 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
             P.max_batches += ((me.num_triangles + std::min(bt, bt_multi) - 1) / std::min(bt, bt_multi)) * groups;
         }
     }
+    if (P.full()) return fail(ctx, CURAST_E_INVALID, "the allocation-free form takes at most 32 instances");
     // stage-1 segments: meshes drawn more than once first (their own launch, whose lanes reuse each
     // loaded triangle over many draws), then the rest; mode 3 sends every mesh to the first
     auto shared_mesh = [&](uint32_t m) { return o.s1_mode == 3 || mesh_draw_count[m] >= 2; };
@@ -562,6 +617,7 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
         const uint32_t part = pass + 1;
         if (any_cmp) P.compressed_parts |= (1u << part) | (all_cmp ? 1u << (part + 8) : 0u);
     }
+    if (P.full()) return fail(ctx, CURAST_E_INVALID, "the allocation-free form takes one mesh and one view");
     P.hdr.n_segs = (uint32_t)P.segs.size();
     P.hdr.n_views = n_views;
     P.hdr.batch_tris = bt;
@@ -625,13 +681,14 @@ TimedFrame* begin_timing(curast_ctx* ctx)
     return &ctx->timed.back();
 }
 
-// Launch the device part of a frame: clear, stage 1, overflow pass, stage 2, stage 3.
-int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, uint32_t grid_share, hipStream_t s, TimedFrame* tf)
+// Launch the device part of a frame over the buffers in `a` (descriptors, queues, counters):
+// clear, stage 1, overflow pass, stage 2, stage 3.  Options other than a.flags come from ctx.
+int launch_frame(curast_ctx* ctx, const RasterArgs& a, uint64_t total_pixels, uint32_t grid1, uint32_t grid_share,
+                 hipStream_t s, TimedFrame* tf)
 {
-    const RasterArgs a = make_args(ctx, P);
-    const bool stats = ctx->opt.flags & kFlagStats;
+    const bool stats = a.flags & kFlagStats;
     const uint32_t cus = (uint32_t)ctx->cus;
-    const uint64_t pairs = (P.total_pixels + 1) / 2;
+    const uint64_t pairs = (total_pixels + 1) / 2;
     const uint32_t clear_grid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>((pairs + 255) / 256, cus * 16ull));
     hipError_t e;
     if (tf) hipEventRecord(tf->ev[0], s);
@@ -653,8 +710,8 @@ int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, uint32_t grid_s
             a1.part = part;
             if (part == 1 && mode == 3) return launch_stage1_share(a1, tpt, stats, grid, s);
             if (mode == 1) return launch_stage1(a1, blk, tpt, stats, grid, s);
-            const bool strips = !(ctx->opt.flags & kFlagNoStrips) && tpt >= 2 &&
-                                (part == 1 || (ctx->opt.flags & kFlagSingleStrips));
+            const bool strips = !(a.flags & kFlagNoStrips) && tpt >= 2 &&
+                                (part == 1 || (a.flags & kFlagSingleStrips));
             return launch_stage1_fast(a1, blk, tpt, strips, stats, grid, s);
         };
         if (grid_share) {
@@ -672,7 +729,7 @@ int launch_frame(curast_ctx* ctx, const Plan& P, uint32_t grid1, uint32_t grid_s
     e = launch_stage2(a, std::max<uint32_t>(1, ctx->opt.s2_waves / 4), stats, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "stage-2 kernel launch");
     if (tf) hipEventRecord(tf->ev[5], s);
-    e = (ctx->opt.flags & kFlagS3PerPart) ? launch_stage3(a, std::max<uint32_t>(1, ctx->opt.s3_blocks), stats, s)
+    e = (a.flags & kFlagS3PerPart) ? launch_stage3(a, std::max<uint32_t>(1, ctx->opt.s3_blocks), stats, s)
                                           : launch_stage3_binned(a, std::max<uint32_t>(1, ctx->opt.s3_blocks), stats, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "stage-3 kernel launch");
     if (tf) {
@@ -707,7 +764,8 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
         HIP_TRY(ctx, hipEventRecord(ctx->raster_stage.ev, s));
         ctx->raster_stage.pending = true;
         const uint64_t shared = P.hdr.shared_batches;
-        rc = launch_frame(ctx, P, grid_for(P.hdr.total_batches - shared), shared ? grid_for(shared) : 0, s, tf);
+        rc = launch_frame(ctx, make_args(ctx, P), P.total_pixels, grid_for(P.hdr.total_batches - shared),
+                          shared ? grid_for(shared) : 0, s, tf);
         return rc;
     }
     // graph path: one captured sequence per structure (sizes of the descriptor block, grid bound,
@@ -732,7 +790,8 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
         HIP_TRY(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
         hipError_t e = hipMemcpyAsync(ctx->raster_stage.dev, ctx->raster_stage.host, P.max_bytes, hipMemcpyHostToDevice,
                                       ctx->capture_stream);
-        int lrc = e == hipSuccess ? launch_frame(ctx, P, grid1, grid1, ctx->capture_stream, nullptr)
+        int lrc = e == hipSuccess ? launch_frame(ctx, make_args(ctx, P), P.total_pixels, grid1, grid1,
+                                                 ctx->capture_stream, nullptr)
                                   : hip_fail(ctx, e, "capture memcpy");
         hipGraph_t graph = nullptr;
         hipError_t e2 = hipStreamEndCapture(ctx->capture_stream, &graph);
@@ -759,6 +818,130 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
         tf->used[kTFrame] = 1;
     }
     return CURAST_OK;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------------------
+// Allocation-free rasterization (curast_rasterize_noalloc)
+// ------------------------------------------------------------------------------------------------
+// One mesh (at most kFixedDraws instances) into one view with no allocation of any kind: the plan
+// is built in fixed arrays on the stack, its descriptors reach the device as the argument of one
+// small kernel, and descriptors, queues, counters and stage-3 bins live in the file-scope device
+// array `scratch` below instead of context buffers.  Host code must not use the array's name as an
+// address (it is a host-side handle): curast_create takes the device address with
+// hipGetSymbolAddress once per device and every use goes through that pointer.  Queues smaller
+// than the context's are safe: overflow falls back to in-place rasterization.
+namespace {
+
+constexpr uint32_t kNaQ2 = 1u << 20;       // stage-2 queue entries (8 MB)
+constexpr uint32_t kNaLarge = 1u << 16;    // large-triangle records (3 MB)
+constexpr uint32_t kNaQ3 = 1u << 19;       // stage-3 tile parts (4 MB + 2 MB of bins)
+constexpr uint32_t kNaTiles = (uint32_t)(kMaxDim / kTileSize) * (uint32_t)(kMaxDim / kTileSize) + 1;
+
+struct NaDesc {
+    FrameHeader hdr;
+    ViewDesc view;
+    MeshDesc mesh;
+    Segment segs[2];
+    DrawDesc draws[kFixedDraws];
+};
+static_assert(sizeof(NaDesc) % 4 == 0 && sizeof(NaDesc) <= 4096, "descriptor block fits one kernel argument");
+
+constexpr size_t kNaOffCounters = align_up(sizeof(NaDesc), 256);
+constexpr size_t kNaOffStats = kNaOffCounters + 256;
+constexpr size_t kNaOffTileCount = kNaOffStats + 256;
+constexpr size_t kNaOffTileOffset = align_up(kNaOffTileCount + sizeof(uint32_t) * kNaTiles, 256);
+constexpr size_t kNaOffQ2 = align_up(kNaOffTileOffset + sizeof(uint32_t) * kNaTiles, 256);
+constexpr size_t kNaOffLarge = align_up(kNaOffQ2 + sizeof(Q2Entry) * kNaQ2, 256);
+constexpr size_t kNaOffQ3 = align_up(kNaOffLarge + sizeof(LargeTri) * kNaLarge, 256);
+constexpr size_t kNaOffBinned = align_up(kNaOffQ3 + sizeof(Q3Entry) * kNaQ3, 256);
+constexpr size_t kNaBytes = align_up(kNaOffBinned + sizeof(uint32_t) * kNaQ3, 256);
+static_assert(kNumCounters * sizeof(unsigned long long) <= 256 && kNumStats * sizeof(unsigned long long) <= 256,
+              "counter areas");
+
+}  // namespace
+
+// The allocation-free form's scratch (about 17 MB per device, held until the process ends).
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+// Copies the frame's descriptor block from the kernel argument into the scratch array.
+__global__ void __launch_bounds__(256) noalloc_descriptor_kernel(NaDesc d, NaDesc* out)
+{
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(&d);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(out);
+    for (uint32_t i = threadIdx.x; i < (uint32_t)(sizeof(NaDesc) / 4); i += blockDim.x) dst[i] = src[i];
+}
+
+namespace {
+
+// Device address of `scratch` on the current device, looked up once per device and kept.
+std::mutex g_scratch_mutex;
+constexpr int kMaxDevices = 64;
+char* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_address(int device, char** out)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = static_cast<char*>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+int rasterize_noalloc(curast_ctx* ctx, const curast_mesh& mesh, const curast_view& view, hipStream_t s)
+{
+    if (!ctx->na_scratch) return fail(ctx, CURAST_E_HIP, "scratch address of the allocation-free form is unknown");
+    if (mesh.instances && mesh.num_instances > kFixedDraws)
+        return fail(ctx, CURAST_E_INVALID, "the allocation-free form takes at most 32 instances");
+    PlanT<FixVec> P;
+    int rc = build_plan(ctx, ctx->opt, &mesh, 1, &view, 1, P);
+    if (rc) return rc;
+    NaDesc d;
+    std::memset(&d, 0, sizeof d);
+    d.hdr = P.hdr;
+    d.view = P.views[0];
+    d.mesh = P.meshes[0];
+    for (size_t i = 0; i < P.segs.size() && i < 2; ++i) d.segs[i] = P.segs[i];
+    for (size_t i = 0; i < P.draws.size(); ++i) d.draws[i] = P.draws[i];
+    char* base = ctx->na_scratch;
+    NaDesc* dd = reinterpret_cast<NaDesc*>(base);
+    RasterArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.hdr = &dd->hdr;
+    a.views = &dd->view;
+    a.meshes = &dd->mesh;
+    a.segs = dd->segs;
+    a.draws = dd->draws;
+    a.counters = reinterpret_cast<unsigned long long*>(base + kNaOffCounters);
+    a.stats = reinterpret_cast<unsigned long long*>(base + kNaOffStats);
+    a.tile_count = reinterpret_cast<uint32_t*>(base + kNaOffTileCount);
+    a.tile_offset = reinterpret_cast<uint32_t*>(base + kNaOffTileOffset);
+    a.q2 = reinterpret_cast<Q2Entry*>(base + kNaOffQ2);
+    a.large = reinterpret_cast<LargeTri*>(base + kNaOffLarge);
+    a.q3 = reinterpret_cast<Q3Entry*>(base + kNaOffQ3);
+    a.q3_binned = reinterpret_cast<uint32_t*>(base + kNaOffBinned);
+    const bool zero = ctx->opt.flags & kFlagZeroQueues;
+    a.q2_cap = zero ? 0 : std::min(ctx->opt.q2_capacity, kNaQ2);
+    a.large_cap = zero ? 0 : std::min(ctx->opt.large_capacity, kNaLarge);
+    a.q3_cap = zero ? 0 : std::min(ctx->opt.q3_capacity, kNaQ3);
+    a.small_px = ctx->opt.small_px;
+    a.medium_px = ctx->opt.medium_px;
+    a.flags = ctx->opt.flags & ~(uint32_t)(kFlagStats | CURAST_FLAG_TIMING);   // no statistics, no events
+    a.s1_mode = ctx->opt.s1_mode;
+    a.part = 0;
+    a.compressed_parts = P.compressed_parts;
+    noalloc_descriptor_kernel<<<1, 256, 0, s>>>(d, dd);
+    HIP_TRY(ctx, hipGetLastError());
+    const uint64_t shared = P.hdr.shared_batches;
+    return launch_frame(ctx, a, P.total_pixels, grid_for(P.hdr.total_batches - shared), shared ? grid_for(shared) : 0,
+                        s, nullptr);
 }
 
 void collect_timings(curast_ctx* ctx)
@@ -917,6 +1100,12 @@ int curast_create(const curast_options* opt, curast_ctx** out)
     if (hipEventCreateWithFlags(&ctx->raster_stage.ev, hipEventDisableTiming) != hipSuccess) return cleanup(CURAST_E_HIP);
     if (hipEventCreateWithFlags(&ctx->resolve_stage.ev, hipEventDisableTiming) != hipSuccess) return cleanup(CURAST_E_HIP);
     if (ensure_queues(ctx)) return cleanup(CURAST_E_OOM);
+    // device address of the allocation-free form's scratch array (looked up once per device)
+    const hipError_t se = scratch_address(ctx->device, &ctx->na_scratch);
+    if (se != hipSuccess) {
+        fprintf(stderr, "curast_create: hipGetSymbolAddress(scratch) failed: %s\n", hipGetErrorString(se));
+        return cleanup(CURAST_E_HIP);
+    }
     *out = ctx;
     return CURAST_OK;
 }
@@ -990,6 +1179,30 @@ int curast_rasterize(curast_ctx* ctx, const float* vertices, uint32_t num_vertic
     v.height = height;
     v.visbuffer = visbuffer;
     return rasterize_impl(ctx, &m, 1, &v, 1, static_cast<hipStream_t>(stream), false);
+}
+
+int curast_rasterize_noalloc(curast_ctx* ctx, const float* vertices, uint32_t num_vertices, const uint32_t* indices,
+                             uint64_t num_triangles, const float* instances, uint32_t num_instances,
+                             const float view_proj[16], float near_plane, int32_t width, int32_t height,
+                             uint64_t* visbuffer, void* stream)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    if (!view_proj) return fail(ctx, CURAST_E_INVALID, "view_proj is NULL");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    curast_mesh m{};
+    m.vertices = vertices;
+    m.num_vertices = num_vertices;
+    m.indices = indices;
+    m.num_triangles = num_triangles;
+    m.instances = instances;
+    m.num_instances = num_instances;
+    curast_view v{};
+    std::memcpy(v.view_proj, view_proj, sizeof(float) * 16);
+    v.near_plane = near_plane;
+    v.width = width;
+    v.height = height;
+    v.visbuffer = visbuffer;
+    return rasterize_noalloc(ctx, m, v, static_cast<hipStream_t>(stream));
 }
 
 int curast_rasterize_batched(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* views,
