@@ -177,6 +177,9 @@ typedef struct {
     uint64_t q3_overflow;       /* (sub-)triangles stage 2 rasterized itself because stage 3 was full */
     uint64_t fragments;         /* covered pixel samples */
     uint64_t atomics;           /* 64-bit atomic minimums issued (the rest skipped by the early-out) */
+    uint64_t strip_draws;       /* (strip, draw) pairs of the multi-draw stage-1 launch's strip path */
+    uint64_t strip_union_pass;  /* of those, strips whose union box may hold a pixel centre (their
+                                   triangles then take the per-triangle test) */
 } curast_stats;
 
 typedef struct curast_ctx curast_ctx;

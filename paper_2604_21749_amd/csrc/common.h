@@ -110,7 +110,7 @@ enum Counter : int {
 enum Stat : int {
     kStTriDraws = 0, kStDrawsCulled, kStCulledNear, kStCulledFrustum, kStCulledTiny,
     kStCulledBack, kStS1Raster, kStQ2, kStQ2Overflow, kStS2Raster, kStQ3, kStQ3Overflow,
-    kStFragments, kStAtomics, kNumStats
+    kStFragments, kStAtomics, kStStripDraws, kStStripPass, kNumStats
 };
 
 // Option flags mirrored from the public header.

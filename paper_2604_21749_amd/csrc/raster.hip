@@ -751,7 +751,9 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                         const bool all_out = !any_nan && fast_reject_union<TPT + 2>(w, V, tiny_cull);
                         if (any_valid) {
                             st.add(kStTriDraws, TPT);
+                            st.add(kStStripDraws);
                             if (all_out) st.add(kStCulledTiny, TPT);
+                            else st.add(kStStripPass);
                         }
                         const bool pass = any_valid && !all_out;
                         const unsigned long long m = __ballot(pass);

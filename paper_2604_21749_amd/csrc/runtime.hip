@@ -100,6 +100,7 @@ struct curast_ctx {
     hipStream_t capture_stream = nullptr;
     std::vector<GraphEntry> graphs;
     std::vector<TimedFrame> timed;
+    std::vector<hipEvent_t> event_pool;   // timing events of collected frames, reused by later frames
     double stage_ms[kNumSlots] = {0};
     uint64_t timed_frames = 0;
     uint64_t draws_culled = 0;
@@ -674,8 +675,21 @@ RasterArgs make_args(curast_ctx* ctx, const Plan& P)
 TimedFrame* begin_timing(curast_ctx* ctx)
 {
     if (!(ctx->opt.flags & CURAST_FLAG_TIMING)) return nullptr;
+    // events come from the context's pool, which grows 32 frames' worth at a time and gets every
+    // event back when the frames are collected (curast_get_stage_times / curast_reset_stage_times),
+    // so a timed frame in steady state costs event records on the stream, not event creation
+    if (ctx->event_pool.size() < kNumSlots + 1)
+        for (int i = 0; i < 32 * (kNumSlots + 1); ++i) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) break;
+            ctx->event_pool.push_back(e);
+        }
+    if (ctx->event_pool.size() < kNumSlots + 1) return nullptr;
     TimedFrame f;
-    for (int i = 0; i <= kNumSlots; ++i) hipEventCreate(&f.ev[i]);
+    for (int i = 0; i <= kNumSlots; ++i) {
+        f.ev[i] = ctx->event_pool.back();
+        ctx->event_pool.pop_back();
+    }
     for (int i = 0; i < kNumSlots; ++i) f.used[i] = 0;
     ctx->timed.push_back(f);
     return &ctx->timed.back();
@@ -965,7 +979,7 @@ void collect_timings(curast_ctx* ctx)
             if (hipEventElapsedTime(&ms, f.ev[7], f.ev[8]) == hipSuccess) ctx->stage_ms[slot] += ms;
         }
         if (f.used[kTClear] || f.used[kTFrame]) ctx->timed_frames++;
-        for (int i = 0; i <= kNumSlots; ++i) hipEventDestroy(f.ev[i]);
+        for (int i = 0; i <= kNumSlots; ++i) ctx->event_pool.push_back(f.ev[i]);
     }
     ctx->timed.clear();
 }
@@ -1122,6 +1136,7 @@ int curast_destroy(curast_ctx* ctx)
         if (st->dev) hipFree(st->dev);
         if (st->ev) hipEventDestroy(st->ev);
     }
+    for (hipEvent_t ev : ctx->event_pool) hipEventDestroy(ev);
     if (ctx->q2) hipFree(ctx->q2);
     if (ctx->q3) hipFree(ctx->q3);
     if (ctx->q3_binned) hipFree(ctx->q3_binned);
@@ -1516,6 +1531,8 @@ int curast_get_stats(curast_ctx* ctx, curast_stats* out)
     out->q3_overflow = s[kStQ3Overflow];
     out->fragments = s[kStFragments];
     out->atomics = s[kStAtomics];
+    out->strip_draws = s[kStStripDraws];
+    out->strip_union_pass = s[kStStripPass];
     return CURAST_OK;
 }
 

@@ -60,7 +60,7 @@ int main(void) {
   P(curast_compressed); O(curast_compressed, index_min); O(curast_compressed, lo); O(curast_compressed, step);
   P(curast_view); O(curast_view, near_plane); O(curast_view, visbuffer);
   P(curast_texture); O(curast_texture, width); O(curast_texture, levels);
-  P(curast_stats); O(curast_stats, atomics);
+  P(curast_stats); O(curast_stats, atomics); O(curast_stats, strip_union_pass);
   return 0;
 }
 '''
@@ -91,6 +91,7 @@ int main(void) {
     assert got["curast_texture.levels"] == api.TextureStruct.levels.offset
     assert got["curast_stats"] == C.sizeof(api.StatsStruct)
     assert got["curast_stats.atomics"] == api.StatsStruct.atomics.offset
+    assert got["curast_stats.strip_union_pass"] == api.StatsStruct.strip_union_pass.offset
 
 
 def test_status_strings_and_version(api):
