@@ -50,10 +50,16 @@ VALU_ISSUE_PEAK = CUS * CLOCK_HZ            # wave64 VALU instructions per secon
 #   reciprocal and two multiplies = 12;
 #   the box test of n window positions: 4 (n - 1) min/max, then 2 margin subtracts, 2 margin adds,
 #   2 floors and 6 compares = 4 (n - 1) + 12;
-#   one (strip of S triangles, draw): S + 2 projections and the union-box test of its S + 2 vertices;
+#   the sphere test of a strip (s1_mode 0 and 2): the centre's projection (12), the two vectors
+#   a - x b (6 FMA), their squared norms (6) and square roots (2), the denominator (1 FMA, 1 multiply,
+#   1 compare), its reciprocal and the radius scale (2), the two radii (2 FMA), the box +- radius (4)
+#   and the extent test (12) = 49;
+#   one (strip of S triangles, draw): the sphere test, then for a strip the sphere cannot reject
+#   S + 2 projections and the union-box test of its S + 2 vertices (s1_mode 4: always the latter);
 #   a strip whose union box may hold a pixel centre: S more box tests of 3 positions (20 each);
 #   a triangle outside a strip (poles, row ends): 3 projections and its box test.
 PROJ_OPS = 12
+SPHERE_OPS = 49
 
 
 def box_ops(n: int) -> int:
@@ -208,7 +214,7 @@ def config_summary(h, rooflines) -> dict:
             "stage_counts": {k: int(h["stats"][k]) for k in (
                 "culled_near", "culled_frustum", "culled_tiny", "culled_backface", "s1_rasterized", "q2_entries",
                 "q2_overflow", "s2_rasterized", "q3_entries", "q3_overflow", "draws_culled", "strip_draws",
-                "strip_union_pass")}}
+                "strip_sphere_pass", "strip_union_pass")}}
 
 
 def run_supersampling(args, api, torch, ctx, gm, attrs, view, ms_plain):
@@ -358,11 +364,16 @@ def multi_launch_ops(h) -> int:
     box may hold a pixel centre, and the triangle x draw items outside strips."""
     o, st = h["options"], h["stats"]
     strips = o["s1_multi_tris_per_thread"] in (2, 4, 8) and not (o["flags"] & 0x100) and o["s1_mode"] != 3
-    S = o["s1_multi_tris_per_thread"] if strips else 1
+    if not strips:
+        return h["multi_items"] * LONE_TRI_DRAW_OPS
+    S = o["s1_multi_tris_per_thread"]
     pairs, passed = int(st["strip_draws"]), int(st["strip_union_pass"])
     lone = max(0, h["multi_items"] - pairs * S)
-    return pairs * strip_draw_ops(S) + passed * S * box_ops(3) + lone * LONE_TRI_DRAW_OPS if strips else \
-        h["multi_items"] * LONE_TRI_DRAW_OPS
+    if o["s1_mode"] in (0, 2):
+        tested = pairs * SPHERE_OPS + int(st["strip_sphere_pass"]) * strip_draw_ops(S)
+    else:
+        tested = pairs * strip_draw_ops(S)
+    return tested + passed * S * box_ops(3) + lone * LONE_TRI_DRAW_OPS
 
 
 def stage1_rooflines(h):
@@ -376,9 +387,11 @@ def stage1_rooflines(h):
     frames."""
     sm = h["stage_ms"]
     o = h["options"]
-    strips = "true" if (o["s1_multi_tris_per_thread"] in (2, 4, 8) and not (o["flags"] & 0x100)) else "false"
-    k_single = f"stage1_fast_kernel<{o['s1_block']}, {o['s1_tris_per_thread']}, false, false, 0>"
-    k_multi = f"stage1_fast_kernel<{o['s1_block']}, {o['s1_multi_tris_per_thread']}, {strips}, false, 0>"
+    strip = o["s1_multi_tris_per_thread"] in (2, 4, 8) and not (o["flags"] & 0x100)
+    sph = "true" if strip and o["s1_mode"] in (0, 2) else "false"
+    k_single = f"stage1_fast_kernel<{o['s1_block']}, {o['s1_tris_per_thread']}, false, false, 0, false>"
+    k_multi = f"stage1_fast_kernel<{o['s1_block']}, {o['s1_multi_tris_per_thread']}, {'true' if strip else 'false'}, " \
+              f"false, 0, {sph}>"
     single_bytes = stage1_algorithmic_bytes(h["single"])
     t_single = max(sm["stage1_single"] * 1e-3, 1e-12)
     t_multi = max(sm["stage1_multi"] * 1e-3, 1e-12)

@@ -104,9 +104,11 @@ typedef struct {
     uint32_t flags;             /* CURAST_FLAG_* */
     uint32_t s1_mode;           /* stage-1 kernel: 0 = auto (currently 2), 1 = one lane per
                                    triangle with exact arithmetic only, 2 = conservative fast reject
-                                   with approximate reciprocals and wave-compacted exact work,
-                                   3 = every mesh through the wave-level vertex-sharing kernel
-                                   (each vertex transformed once per wave and draw) */
+                                   with approximate reciprocals and wave-compacted exact work, where
+                                   a strip of the multi-draw launch is first tested through the
+                                   bounding sphere of its vertices, 3 = every mesh through the
+                                   wave-level vertex-sharing kernel (each vertex transformed once
+                                   per wave and draw), 4 = as 2 without the strip spheres */
     uint32_t s1_multi_tris_per_thread; /* as s1_tris_per_thread (1, 2, 4 or 8; 1, 2 or 4 with
                                    s1_mode 3), for meshes with two or more surviving draws, which
                                    stage 1 takes in a launch of its own; with 2 or more, a lane's
@@ -180,6 +182,8 @@ typedef struct {
     uint64_t strip_draws;       /* (strip, draw) pairs of the multi-draw stage-1 launch's strip path */
     uint64_t strip_union_pass;  /* of those, strips whose union box may hold a pixel centre (their
                                    triangles then take the per-triangle test) */
+    uint64_t strip_sphere_pass; /* (strip, draw) pairs whose bounding-sphere test could not reject
+                                   the strip (they then take the union-box test; s1_mode 0 and 2) */
 } curast_stats;
 
 typedef struct curast_ctx curast_ctx;

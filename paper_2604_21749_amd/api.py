@@ -73,7 +73,7 @@ class StatsStruct(C.Structure):
     _fields_ = [(n, C.c_uint64) for n in (
         "tri_draws", "draws_culled", "culled_near", "culled_frustum", "culled_tiny", "culled_backface",
         "s1_rasterized", "q2_entries", "q2_overflow", "s2_rasterized", "q3_entries", "q3_overflow",
-        "fragments", "atomics", "strip_draws", "strip_union_pass")]
+        "fragments", "atomics", "strip_draws", "strip_union_pass", "strip_sphere_pass")]
 
 
 # Every entry point of include/curast.h with its ctypes signature.

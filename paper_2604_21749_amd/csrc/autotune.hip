@@ -185,7 +185,7 @@ extern "C" int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint3
         std::vector<uint32_t> values;
     };
     std::vector<Axis> axes = {
-        {&curast_options::s1_mode, {0, 1, 2, 3}},
+        {&curast_options::s1_mode, {0, 1, 2, 3, 4}},
         {&curast_options::s1_block, {64, 128, 256, 512}},
         {&curast_options::s1_tris_per_thread, {1, 2, 4, 8}},
         {&curast_options::s1_blocks_per_cu, {256, 1024, 2048, 4096}},

@@ -73,12 +73,15 @@ struct Segment {                  // 32 B
 // Bit 31 of `view` (kDrawInterior) marks draws whose bounding sphere the host proved to lie in
 // front of the near plane and inside |x|, |y| <= 1.99 w: no vertex of such a draw needs the
 // per-vertex near/guard tests of the fast stage-1 path.
-struct DrawDesc {                 // 96 B
+struct DrawDesc {                 // 112 B
     float A[12];                  // rows x, y, w of VP * X (the exact transform)
     float R[8];                   // interior draws: hW (row x + row w), hH (row y + row w)
     uint64_t id_base;
     uint32_t view;                // view index | kDrawInterior
     uint32_t mesh;
+    float wnorm;                  // interior draws: |(A[8], A[9], A[10])| rounded up (strip spheres)
+    float slack;                  // interior draws: pixels added to a strip sphere's projected radius
+    float wmax, hmax;             // W - 1, H - 1 of the view (copied, so the sphere test reads one record)
 };
 constexpr uint32_t kDrawInterior = 0x80000000u;
 constexpr uint32_t kDrawViewMask = 0x7FFFFFFFu;
@@ -110,7 +113,7 @@ enum Counter : int {
 enum Stat : int {
     kStTriDraws = 0, kStDrawsCulled, kStCulledNear, kStCulledFrustum, kStCulledTiny,
     kStCulledBack, kStS1Raster, kStQ2, kStQ2Overflow, kStS2Raster, kStQ3, kStQ3Overflow,
-    kStFragments, kStAtomics, kStStripDraws, kStStripPass, kNumStats
+    kStFragments, kStAtomics, kStStripDraws, kStStripPass, kStSpherePass, kNumStats
 };
 
 // Option flags mirrored from the public header.
@@ -139,7 +142,8 @@ struct RasterArgs {
     uint32_t q2_cap, large_cap, q3_cap;
     uint32_t small_px, medium_px;
     uint32_t flags;
-    uint32_t s1_mode;             // 0 auto (= 2), 1 exact only, 2 fast reject, 3 vertex sharing for every mesh
+    uint32_t s1_mode;             // 0 auto (= 2), 1 exact only, 2 fast reject (strip spheres in the
+                                  // multi-draw launch), 3 vertex sharing for every mesh, 4 as 2 without spheres
     uint32_t part;                // stage-1 work items: 0 all, 1 the shared prefix, 2 the rest
     uint32_t* tile_count;         // [n_tiles] parts per tile (zeroed by the clear kernel)
     uint32_t* tile_offset;        // [n_tiles + 1] exclusive prefix of tile_count

@@ -609,6 +609,16 @@ __device__ __forceinline__ bool fast_reject_union(const float2 (&w)[N], const Vi
     return fast_reject_extent(x0, x1, y0, y1, V, tiny_cull);
 }
 
+// Strip spheres.  Before a strip of an interior draw is projected vertex by vertex, it is tested
+// through a bounding sphere (c, r) of its vertices, computed once per work item in object space.
+// For a vertex v = c + d, |d| <= r, with a = (row x'')[0..2] and b = (row w)[0..2] of the draw,
+//   x(v) - x(c) = ((a - x(c) b) . d) / (w(c) + b . d),  so  |x(v) - x(c)| <= |a - x(c) b| r / (w(c) - |b| r)
+// (and likewise y), provided w(c) - |b| r > 0; the test requires at least w(c) / 2.  The box
+// x(c) +- that bound, widened by the per-draw slack the host derived for the binary32 error of the
+// projected centre and of the box arithmetic (DrawDesc::slack), holds every exact window position of
+// the strip's vertices up to kFastMargin, so the extent test of the union box applies to it.  The
+// radius itself is inflated by 2^-10 in relative terms, which covers the few roundings in r, the
+// norms, the reciprocal and the products below.  A rejected strip covers no pixel centre.
 // A strip whose union box may hold a pixel centre, waiting for its per-triangle tests: the
 // window positions of its N vertices for one draw, the draw and its first triangle.
 template <int N>
@@ -617,18 +627,113 @@ struct StripEntry {
     uint32_t draw, tri;
 };
 
-template <int BLOCK, int TPT, bool STRIPS, bool STATS, int CMP>
+// A (draw, lane) pair of the stage-1 strip path whose sphere test could not reject the strip of
+// that lane of the wavefront: it waits in LDS for the union-box and per-triangle tests.
+struct StripPair {
+    uint32_t draw, lane;
+};
+
+// What the sphere test reads of a draw and its view, loaded one draw ahead of its use.
+struct SphereDraw {
+    float Rx[4], Ry[4], Aw[4];
+    float wnorm, slack, wmax, hmax;
+    uint32_t view;
+};
+
+__device__ __forceinline__ SphereDraw sphere_draw(const DrawDesc* __restrict__ d_draws, uint32_t d)
+{
+    const DrawDesc& D = d_draws[d];
+    SphereDraw s;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        s.Rx[k] = D.R[k];
+        s.Ry[k] = D.R[4 + k];
+        s.Aw[k] = D.A[8 + k];
+    }
+    s.wnorm = D.wnorm;
+    s.slack = D.slack;
+    s.view = D.view;
+    s.wmax = D.wmax;
+    s.hmax = D.hmax;
+    return s;
+}
+
+__device__ __forceinline__ bool sphere_reject(const SphereDraw& D, const float (&c)[3], float r, bool tiny_cull)
+{
+    const float* Rx = D.Rx;
+    const float* Ry = D.Ry;
+    const float* Aw = D.Aw;
+    const float w = row_dot(Aw, c[0], c[1], c[2]);
+    const float rw = __builtin_amdgcn_rcpf(w);
+    const float xc = row_dot(Rx, c[0], c[1], c[2]) * rw;
+    const float yc = row_dot(Ry, c[0], c[1], c[2]) * rw;
+    const float ex0 = __builtin_fmaf(-xc, Aw[0], Rx[0]), ex1 = __builtin_fmaf(-xc, Aw[1], Rx[1]),
+                ex2 = __builtin_fmaf(-xc, Aw[2], Rx[2]);
+    const float ey0 = __builtin_fmaf(-yc, Aw[0], Ry[0]), ey1 = __builtin_fmaf(-yc, Aw[1], Ry[1]),
+                ey2 = __builtin_fmaf(-yc, Aw[2], Ry[2]);
+    const float nx = __builtin_amdgcn_sqrtf(__builtin_fmaf(ex2, ex2, __builtin_fmaf(ex1, ex1, ex0 * ex0)));
+    const float ny = __builtin_amdgcn_sqrtf(__builtin_fmaf(ey2, ey2, __builtin_fmaf(ey1, ey1, ey0 * ey0)));
+    const float den = __builtin_fmaf(-D.wnorm, r, w);
+    const float t = r * __builtin_amdgcn_rcpf(den);
+    const float rx = __builtin_fmaf(nx, t, D.slack), ry = __builtin_fmaf(ny, t, D.slack);
+    // the extent test of fast_reject_extent on the box xc +- rx, yc +- ry, without branches
+    const float lx = (xc - rx) - (kFastMargin + 0.5f);
+    const float fx = __builtin_floorf((xc + rx) + (kFastMargin - 0.5f));
+    const float ly = (yc - ry) - (kFastMargin + 0.5f);
+    const float fy = __builtin_floorf((yc + ry) + (kFastMargin - 0.5f));
+    const bool outside = (fx < 0.0f) | (lx > D.wmax) | (fy < 0.0f) | (ly > D.hmax);
+    const bool empty = (fx < lx) | (fy < ly);
+    return (den >= 0.5f * w) & (outside | (tiny_cull & empty));
+}
+
+// Object-space bounding sphere of N points: their mean (a convex combination, so it lies inside
+// the mesh's bounding sphere like the points, where the host's per-draw bounds hold) and the largest
+// distance to it, inflated by 2^-10 (see sphere_reject).
+template <int N>
+__device__ __forceinline__ void strip_sphere(const float (&q)[N][3], float (&c)[3], float& r)
+{
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        float sum = q[0][j];
+#pragma unroll
+        for (int i = 1; i < N; ++i) sum += q[i][j];
+        c[j] = sum * (1.0f / (float)N);
+    }
+    float r2 = 0.0f;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const float d0 = q[i][0] - c[0], d1 = q[i][1] - c[1], d2 = q[i][2] - c[2];
+        r2 = fmaxf(r2, __builtin_fmaf(d2, d2, __builtin_fmaf(d1, d1, d0 * d0)));
+    }
+    r = __builtin_amdgcn_sqrtf(r2) * (1.0f + 1.0f / 1024.0f);
+}
+
+template <int BLOCK, int TPT, bool STRIPS, bool STATS, int CMP, bool SPH>
 __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST_DESC_PARAMS)
 {
     static_assert(!STRIPS || TPT == 2 || TPT == 4 || TPT == 8, "strips of 2, 4 or 8 triangles per lane");
+    static_assert(STRIPS || !SPH, "strip spheres need strips");
     constexpr int WAVES = BLOCK / 64;
     using Entry = typename std::conditional<STRIPS, IdEntry, ClipEntry>::type;
+    constexpr int NV = TPT + 2;   // vertices of a strip
     __shared__ Entry s_ring[WAVES][kRing];
-    // strips that fail the union test gather here, 64 at a time, so that their per-triangle tests
-    // run with every lane busy instead of on the few failing lanes of a draw
-    __shared__ StripEntry<TPT + 2> s_strip[WAVES][STRIPS ? kRing : 1];
-    StripEntry<TPT + 2>* sring = s_strip[threadIdx.x >> 6];
-    uint32_t shead = 0, stail = 0;   // wave-uniform
+    // Strips that a per-draw test could not reject gather in LDS, 64 at a time, so that their
+    // per-triangle tests run with every lane busy instead of on the few failing lanes of a draw.
+    // Union-box strips keep their window positions (StripRing).  Sphere strips (SPH) keep (draw,
+    // lane) pairs and every lane's strip vertices for the work item, so the lane that drains a pair
+    // projects another lane's strip (StripStore).
+    struct StripRing {
+        StripEntry<NV> e[kRing];
+    };
+    struct StripStore {
+        float q[64][3 * NV];
+        StripPair ring[kRing];
+    };
+    using StripLds =
+        typename std::conditional<!STRIPS, char, typename std::conditional<SPH, StripStore, StripRing>::type>::type;
+    __shared__ StripLds s_strip[WAVES];
+    StripLds& slds = s_strip[threadIdx.x >> 6];
+    uint32_t shead = 0, stail = 0;   // wave-uniform (union-box strips)
     const FrameHeader hdr = *d_hdr;
     uint64_t first, total;
     work_range(hdr, a.part, first, total);
@@ -674,12 +779,13 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
         if constexpr (decltype(interior_tag)::value) return fast_reject_box(x, y, z, V, tiny_cull);
         else return fast_reject(x, y, z, V, tiny_cull);
     };
-    // per-triangle tests of n gathered strips, one strip per lane; survivors go to the exact path
+    // per-triangle tests of n gathered union-box strips, one strip per lane; survivors go to the
+    // exact path
     auto drain_strips = [&](uint32_t n) __attribute__((always_inline)) {
-        if constexpr (STRIPS) {
+        if constexpr (STRIPS && !SPH) {
             const uint32_t lane = threadIdx.x & 63;
             const bool have = lane < n;
-            const StripEntry<TPT + 2> e = sring[(shead + lane) & (kRing - 1)];
+            const StripEntry<NV> e = slds.e[(shead + lane) & (kRing - 1)];
             const uint32_t dd = have ? e.draw : 0u;
             const DrawDesc& D = d_draws[dd];
             const ViewDesc V = d_views[D.view & kDrawViewMask];
@@ -692,6 +798,48 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                                           : fast_reject(e.w[k], e.w[k + 1], e.w[k + 2], V, tiny_cull);
                 if (have && rej) st.add(kStCulledTiny);
                 push(have && !rej, dd, e.tri + (uint32_t)k, fill_mesh);
+            }
+        }
+    };
+    // the union-box and per-triangle tests of n gathered (draw, lane) pairs of sphere strips, one per
+    // lane: the lane projects the strip of lane `src` of its wavefront for draw `dd` (interior or
+    // general); survivors go to the exact path
+    auto drain_pairs = [&](uint32_t head, uint32_t n, uint64_t tb, uint32_t mesh_id, uint32_t d_any)
+        __attribute__((always_inline)) {
+        if constexpr (SPH) {
+            const uint32_t lane = threadIdx.x & 63;
+            const bool have = lane < n;
+            const StripPair e = slds.ring[(head + lane) & (kRing - 1)];
+            const uint32_t dd = have ? e.draw : d_any;
+            const uint32_t src = have ? e.lane : 0u;
+            const DrawDesc& D = d_draws[dd];
+            const ViewDesc V = d_views[D.view & kDrawViewMask];
+            const bool interior = (D.view & kDrawInterior) != 0;
+            float2 w[NV];
+            bool any_nan = false;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const float* qq = &slds.q[src][3 * i];
+                const float q0 = qq[0], q1 = qq[1], q2 = qq[2];
+                w[i] = interior ? fast_window_prescaled(D.R, D.A + 8, q0, q1, q2)
+                                : fast_window(transform(D.A, q0, q1, q2), V);
+                any_nan |= __builtin_isnan(w[i].x);
+            }
+            const bool all_out = !any_nan && fast_reject_union<NV>(w, V, tiny_cull);
+            if (have) {
+                if (all_out) st.add(kStCulledTiny, TPT);
+                else st.add(kStStripPass);
+            }
+            const bool pass = have && !all_out;
+            const uint32_t tri0 =
+                (uint32_t)(tb * (uint64_t)(BLOCK * TPT) + (uint64_t)(((threadIdx.x & ~63u) + src) * TPT));
+            auto fill_mesh = [&](IdEntry& x) { x.mesh = mesh_id; };
+#pragma unroll
+            for (int k = 0; k < TPT; ++k) {
+                const bool rej = interior ? fast_reject_box(w[k], w[k + 1], w[k + 2], V, tiny_cull)
+                                          : fast_reject(w[k], w[k + 1], w[k + 2], V, tiny_cull);
+                if (pass && rej) st.add(kStCulledTiny);
+                push(pass && !rej, dd, tri0 + (uint32_t)k, fill_mesh);
             }
         }
     };
@@ -735,47 +883,126 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                 for (int i = 0; i < TPT + 2; ++i) {
                     mesh_vertex<CMP>(mesh, any_valid ? sv[i] : 0u, q[i]);
                 }
-#pragma unroll 1
-                for (uint32_t d = d0; d < d1; ++d) {
-                    const DrawDesc& D = d_draws[d];
-                    const ViewDesc V = d_views[D.view & kDrawViewMask];
-                    auto body = [&](auto tag) {
-                        constexpr bool INTERIOR = decltype(tag)::value;
-                        float2 w[TPT + 2];
-                        bool any_nan = false;
+                if constexpr (SPH) {
+                    // this lane's strip vertices, for the lane that drains one of its (draw, lane) pairs
+                    const uint32_t lane = threadIdx.x & 63;
 #pragma unroll
-                        for (int i = 0; i < TPT + 2; ++i) {
-                            w[i] = window(tag, D, V, q[i]);
-                            if constexpr (!INTERIOR) any_nan |= __builtin_isnan(w[i].x);
-                        }
-                        const bool all_out = !any_nan && fast_reject_union<TPT + 2>(w, V, tiny_cull);
-                        if (any_valid) {
-                            st.add(kStTriDraws, TPT);
-                            st.add(kStStripDraws);
-                            if (all_out) st.add(kStCulledTiny, TPT);
-                            else st.add(kStStripPass);
-                        }
-                        const bool pass = any_valid && !all_out;
-                        const unsigned long long m = __ballot(pass);
-                        if (m) {
-                            if (pass) {
-                                StripEntry<TPT + 2>& se = sring[(stail + rank_in(m)) & (kRing - 1)];
-#pragma unroll
-                                for (int i = 0; i < TPT + 2; ++i) se.w[i] = w[i];
-                                se.draw = d;
-                                se.tri = tri[0];
+                    for (int i = 0; i < NV; ++i) {
+                        slds.q[lane][3 * i] = q[i][0];
+                        slds.q[lane][3 * i + 1] = q[i][1];
+                        slds.q[lane][3 * i + 2] = q[i][2];
+                    }
+                    float sc[3], sr;
+                    strip_sphere<NV>(q, sc, sr);
+                    uint32_t phead = 0, ptail = 0;   // wave-uniform
+                    // pairs of draws dbase + j for the set bits j of `bits` go to the ring, a few rounds of
+                    // compaction per 32 draws instead of one per draw
+                    auto flush = [&](uint32_t bits, uint32_t dbase) __attribute__((always_inline)) {
+                        while (__ballot(bits != 0u)) {
+                            const bool has = bits != 0u;
+                            const uint32_t j = has ? (uint32_t)__builtin_ctz(bits) : 0u;
+                            bits &= bits - 1u;
+                            const unsigned long long m = __ballot(has);
+                            if (has) {
+                                StripPair& pe = slds.ring[(ptail + rank_in(m)) & (kRing - 1)];
+                                pe.draw = dbase + j;
+                                pe.lane = lane;
                             }
-                            stail += (uint32_t)__popcll(m);
-                            if (stail - shead >= 64) {
+                            ptail += (uint32_t)__popcll(m);
+                            if (ptail - phead >= 64) {
                                 wave_lds_sync();
-                                drain_strips(64);
-                                shead += 64;
+                                drain_pairs(phead, 64, tb, wi.mesh, d0);
+                                phead += 64;
                                 wave_lds_sync();
                             }
                         }
                     };
-                    if (D.view & kDrawInterior) body(std::true_type{});
-                    else body(std::false_type{});
+#pragma unroll 1
+                    for (uint32_t dc = d0; dc < d1; dc += 32) {
+                        const uint32_t dn = min(32u, d1 - dc);
+                        uint32_t bits = 0;
+#pragma unroll 1
+                        for (uint32_t j = 0; j < dn; ++j) {
+                            const uint32_t d = dc + j;
+                            const DrawDesc& D = d_draws[d];
+                            const ViewDesc V = d_views[D.view & kDrawViewMask];
+                            bool pass;
+                            if (D.view & kDrawInterior) {
+                                // the strip's bounding sphere first (see sphere_reject)
+                                pass = any_valid && !sphere_reject(sphere_draw(d_draws, d), sc, sr, tiny_cull);
+                                if (any_valid && pass) st.add(kStSpherePass);
+                            } else {
+                                // the box around the strip's TPT + 2 window positions holds each triangle's box
+                                auto body = [&](auto tag) {
+                                    constexpr bool INTERIOR = decltype(tag)::value;
+                                    float2 w[NV];
+                                    bool any_nan = false;
+#pragma unroll
+                                    for (int i = 0; i < NV; ++i) {
+                                        w[i] = window(tag, D, V, q[i]);
+                                        if constexpr (!INTERIOR) any_nan |= __builtin_isnan(w[i].x);
+                                    }
+                                    return !any_nan && fast_reject_union<NV>(w, V, tiny_cull);
+                                };
+                                const bool all_out =
+                                    (D.view & kDrawInterior) ? body(std::true_type{}) : body(std::false_type{});
+                                pass = any_valid && !all_out;
+                            }
+                            if (any_valid) {
+                                st.add(kStTriDraws, TPT);
+                                st.add(kStStripDraws);
+                                if (!pass) st.add(kStCulledTiny, TPT);
+                            }
+                            bits |= (uint32_t)pass << j;
+                        }
+                        flush(bits, dc);
+                    }
+                    wave_lds_sync();
+                    if (ptail != phead) drain_pairs(phead, ptail - phead, tb, wi.mesh, d0);
+                    wave_lds_sync();
+                } else {
+#pragma unroll 1
+                    for (uint32_t d = d0; d < d1; ++d) {
+                        const DrawDesc& D = d_draws[d];
+                        const ViewDesc V = d_views[D.view & kDrawViewMask];
+                        auto body = [&](auto tag) {
+                            constexpr bool INTERIOR = decltype(tag)::value;
+                            float2 w[TPT + 2];
+                            bool any_nan = false;
+#pragma unroll
+                            for (int i = 0; i < TPT + 2; ++i) {
+                                w[i] = window(tag, D, V, q[i]);
+                                if constexpr (!INTERIOR) any_nan |= __builtin_isnan(w[i].x);
+                            }
+                            const bool all_out = !any_nan && fast_reject_union<TPT + 2>(w, V, tiny_cull);
+                            if (any_valid) {
+                                st.add(kStTriDraws, TPT);
+                                st.add(kStStripDraws);
+                                if (all_out) st.add(kStCulledTiny, TPT);
+                                else st.add(kStStripPass);
+                            }
+                            const bool pass = any_valid && !all_out;
+                            const unsigned long long m = __ballot(pass);
+                            if (m) {
+                                if (pass) {
+                                    StripEntry<TPT + 2>& se = slds.e[(stail + rank_in(m)) & (kRing - 1)];
+#pragma unroll
+                                    for (int i = 0; i < TPT + 2; ++i) se.w[i] = w[i];
+                                    se.draw = d;
+                                    se.tri = tri[0];
+                                }
+                                stail += (uint32_t)__popcll(m);
+                                if (stail - shead >= 64) {
+                                    wave_lds_sync();
+                                    drain_strips(64);
+                                    shead += 64;
+                                    wave_lds_sync();
+                                }
+                            }
+                        };
+                        if (D.view & kDrawInterior) body(std::true_type{});
+                        else body(std::false_type{});
+                    }
                 }
                 continue;
             }
@@ -871,7 +1098,7 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
             }
         }
     }
-    if constexpr (STRIPS) {
+    if constexpr (STRIPS && !SPH) {
         if (stail != shead) {
             wave_lds_sync();
             drain_strips(stail - shead);
@@ -1433,42 +1660,48 @@ hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool
 
 // Launches whose meshes are all plain or all compressed use a kernel without the per-mesh
 // compression branch (Sec. 4.6 notes the same for its kernels); mixed launches decide per mesh.
-template <int BLOCK, int TPT, bool STRIPS>
+template <int BLOCK, int TPT, bool STRIPS, bool SPH>
 static hipError_t stage1_fast_dispatch(const RasterArgs& a, bool stats, uint32_t grid, hipStream_t s)
 {
     // the statistics variants (a measurement aid) decide per mesh, which is right for any launch
     const bool any = (a.compressed_parts >> a.part) & 1u, all = (a.compressed_parts >> (a.part + 8)) & 1u;
-    if (stats) stage1_fast_kernel<BLOCK, TPT, STRIPS, true, -1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
-    else if (all) stage1_fast_kernel<BLOCK, TPT, STRIPS, false, 1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
-    else if (any) stage1_fast_kernel<BLOCK, TPT, STRIPS, false, -1><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
-    else stage1_fast_kernel<BLOCK, TPT, STRIPS, false, 0><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    if (stats) stage1_fast_kernel<BLOCK, TPT, STRIPS, true, -1, SPH><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    else if (all) stage1_fast_kernel<BLOCK, TPT, STRIPS, false, 1, SPH><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    else if (any) stage1_fast_kernel<BLOCK, TPT, STRIPS, false, -1, SPH><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
+    else stage1_fast_kernel<BLOCK, TPT, STRIPS, false, 0, SPH><<<grid, BLOCK, 0, s>>>(a, CURAST_DESC_ARGS(a));
     return hipGetLastError();
 }
 
+template <int BLOCK, int TPT>
+static hipError_t stage1_fast_strips(const RasterArgs& a, bool strips, bool spheres, bool stats, uint32_t grid,
+                                     hipStream_t s)
+{
+    if (!strips) return stage1_fast_dispatch<BLOCK, TPT, false, false>(a, stats, grid, s);
+    return spheres ? stage1_fast_dispatch<BLOCK, TPT, true, true>(a, stats, grid, s)
+                   : stage1_fast_dispatch<BLOCK, TPT, true, false>(a, stats, grid, s);
+}
+
 template <int BLOCK>
-static hipError_t stage1_fast_tpt(const RasterArgs& a, uint32_t tpt, bool strips, bool stats, uint32_t grid,
-                                  hipStream_t s)
+static hipError_t stage1_fast_tpt(const RasterArgs& a, uint32_t tpt, bool strips, bool spheres, bool stats,
+                                  uint32_t grid, hipStream_t s)
 {
     switch (tpt) {
-    case 1: return stage1_fast_dispatch<BLOCK, 1, false>(a, stats, grid, s);
-    case 2: return strips ? stage1_fast_dispatch<BLOCK, 2, true>(a, stats, grid, s)
-                          : stage1_fast_dispatch<BLOCK, 2, false>(a, stats, grid, s);
-    case 4: return strips ? stage1_fast_dispatch<BLOCK, 4, true>(a, stats, grid, s)
-                          : stage1_fast_dispatch<BLOCK, 4, false>(a, stats, grid, s);
-    case 8: return strips ? stage1_fast_dispatch<BLOCK, 8, true>(a, stats, grid, s)
-                          : stage1_fast_dispatch<BLOCK, 8, false>(a, stats, grid, s);
+    case 1: return stage1_fast_dispatch<BLOCK, 1, false, false>(a, stats, grid, s);
+    case 2: return stage1_fast_strips<BLOCK, 2>(a, strips, spheres, stats, grid, s);
+    case 4: return stage1_fast_strips<BLOCK, 4>(a, strips, spheres, stats, grid, s);
+    case 8: return stage1_fast_strips<BLOCK, 8>(a, strips, spheres, stats, grid, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool strips, bool stats, uint32_t grid,
-                              hipStream_t s)
+hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool strips, bool spheres, bool stats,
+                              uint32_t grid, hipStream_t s)
 {
     switch (block) {
-    case 64: return stage1_fast_tpt<64>(a, tpt, strips, stats, grid, s);
-    case 128: return stage1_fast_tpt<128>(a, tpt, strips, stats, grid, s);
-    case 256: return stage1_fast_tpt<256>(a, tpt, strips, stats, grid, s);
-    case 512: return stage1_fast_tpt<512>(a, tpt, strips, stats, grid, s);
+    case 64: return stage1_fast_tpt<64>(a, tpt, strips, spheres, stats, grid, s);
+    case 128: return stage1_fast_tpt<128>(a, tpt, strips, spheres, stats, grid, s);
+    case 256: return stage1_fast_tpt<256>(a, tpt, strips, spheres, stats, grid, s);
+    case 512: return stage1_fast_tpt<512>(a, tpt, strips, spheres, stats, grid, s);
     default: return hipErrorInvalidValue;
     }
 }

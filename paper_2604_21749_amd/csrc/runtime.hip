@@ -25,8 +25,8 @@
 namespace curast {
 hipError_t launch_clear(const RasterArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_stage1(const RasterArgs& a, uint32_t block, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s);
-hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool strips, bool stats, uint32_t grid,
-                              hipStream_t s);
+hipError_t launch_stage1_fast(const RasterArgs& a, uint32_t block, uint32_t tpt, bool strips, bool spheres, bool stats,
+                              uint32_t grid, hipStream_t s);
 hipError_t launch_stage1_share(const RasterArgs& a, uint32_t tpt, bool stats, uint32_t grid, hipStream_t s);
 hipError_t launch_stage1_overflow(const RasterArgs& a, uint32_t grid, hipStream_t s);
 hipError_t launch_stage2(const RasterArgs& a, uint32_t grid, bool stats, hipStream_t s);
@@ -143,7 +143,7 @@ int validate_options(const curast_options& o, std::string& msg)
     if (o.s1_mode == 3 && o.s1_multi_tris_per_thread == 8)
         return bad("s1_mode 3 takes s1_multi_tris_per_thread 1, 2 or 4");
     if (o.small_px > 65536) return bad("small_px must be <= 65536");
-    if (o.s1_mode > 3) return bad("s1_mode must be 0, 1, 2 or 3");
+    if (o.s1_mode > 4) return bad("s1_mode must be 0, 1, 2, 3 or 4");
     if (o.s1_draws_per_item > 65536) return bad("s1_draws_per_item must be <= 65536");
     if (o.s1_blocks_per_cu > 65536) return bad("s1_blocks_per_cu must be <= 65536");
     if (o.q2_capacity > (1u << 30) || o.q3_capacity > (1u << 30) || o.large_capacity > (1u << 28))
@@ -349,7 +349,7 @@ bool sphere_interior(const float A[12], const float bs[4], float near_plane)
 // snapping and (3 hW + 1) u of box arithmetic, 1% slack) may exceed the fast margin of 1/32 px
 // anywhere in the bounding sphere; S_r bounds sum_j |row_rj| |v_j| + |row_r3| over the sphere and
 // w is bounded below by its smallest depth.
-bool prescaled_rows(const float A[12], const float bs[4], float hW, float hH, float R[8])
+bool prescaled_rows(const float A[12], const float bs[4], float hW, float hH, float R[8], float* wnorm, float* slack)
 {
     const double u = std::ldexp(1.0, -24);
     const double c[3] = {bs[0], bs[1], bs[2]}, r = bs[3];
@@ -376,6 +376,16 @@ bool prescaled_rows(const float A[12], const float bs[4], float hW, float hH, fl
         R[k] = (float)((double)hW * ((double)A[k] + (double)A[8 + k]));
         R[4 + k] = (float)((double)hH * ((double)A[4 + k] + (double)A[8 + k]));
     }
+    // strip spheres (stage 1, multi-draw launch): |(w row)| rounded up, and the pixels a sphere's
+    // projected radius gets on top, which cover the binary32 error of the projected centre
+    // (3.01u S_R / w + |x| (3.01u S_w / w + 3u) with S_R <= hW (S_x + S_w) and |x| <= 3 hW), the same
+    // error carried into the radius, and two roundings of box arithmetic at |x| <= 3 hW
+    *wnorm = std::nextafter((float)std::sqrt((double)A[8] * A[8] + (double)A[9] * A[9] + (double)A[10] * A[10]),
+                            INFINITY);
+    auto slack_of = [&](double h, double s_row) {
+        return 2.0 * h * u * (3.01 * s_row / w_lo + 12.04 * sw / w_lo + 9.0) + 6.0 * h * u;
+    };
+    *slack = std::nextafter((float)(1.01 * std::max(slack_of(hW, sx), slack_of(hH, sy))), INFINITY);
     return true;
 }
 
@@ -567,10 +577,13 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
                 draw_matrix(views[v].view_proj, me.instances ? me.instances + 12ull * i : nullptr, D.A);
                 const bool out = cull && sphere_outside(D.A, me.bsphere, views[v].near_plane);
                 for (int k = 0; k < 8; ++k) D.R[k] = 0.0f;
+                D.wnorm = D.slack = 0.0f;
+                D.wmax = (float)(views[v].width - 1);
+                D.hmax = (float)(views[v].height - 1);
                 const bool inner = !out && !(o.flags & kFlagNoFastInterior) &&
                                    sphere_interior(D.A, me.bsphere, views[v].near_plane) &&
                                    prescaled_rows(D.A, me.bsphere, 0.5f * (float)views[v].width,
-                                                  0.5f * (float)views[v].height, D.R);
+                                                  0.5f * (float)views[v].height, D.R, &D.wnorm, &D.slack);
                 if (visible) visible[(P.pair_count + i) * (uint64_t)n_views + v] = out ? 0 : inner ? 2 : 1;
                 if (out) {
                     P.draws_culled++;
@@ -726,7 +739,9 @@ int launch_frame(curast_ctx* ctx, const RasterArgs& a, uint64_t total_pixels, ui
             if (mode == 1) return launch_stage1(a1, blk, tpt, stats, grid, s);
             const bool strips = !(a.flags & kFlagNoStrips) && tpt >= 2 &&
                                 (part == 1 || (a.flags & kFlagSingleStrips));
-            return launch_stage1_fast(a1, blk, tpt, strips, stats, grid, s);
+            // strip spheres in the multi-draw launch, s1_mode 0 and 2 (s1_mode 4: union boxes only)
+            const bool spheres = strips && part == 1 && mode != 4;
+            return launch_stage1_fast(a1, blk, tpt, strips, spheres, stats, grid, s);
         };
         if (grid_share) {
             e = launch_part(1, ctx->opt.s1_multi_tris_per_thread, grid_share);
@@ -1533,6 +1548,7 @@ int curast_get_stats(curast_ctx* ctx, curast_stats* out)
     out->atomics = s[kStAtomics];
     out->strip_draws = s[kStStripDraws];
     out->strip_union_pass = s[kStStripPass];
+    out->strip_sphere_pass = s[kStSpherePass];
     return CURAST_OK;
 }
 

@@ -98,6 +98,8 @@ OPTION_SWEEP = [
     dict(s1_multi_tris_per_thread=8, s1_block=512, s1_draws_per_item=3, flags=api.FLAG_STATS),
     dict(s1_blocks_per_cu=1), dict(s1_blocks_per_cu=1, s1_mode=1, s1_block=512),
     dict(s1_blocks_per_cu=3, s1_mode=3), dict(s1_blocks_per_cu=65536),
+    dict(s1_mode=4), dict(s1_mode=4, s1_multi_tris_per_thread=8), dict(s1_mode=2, s1_multi_tris_per_thread=8, s1_block=256),
+    dict(s1_mode=4, flags=api.FLAG_ZERO_QUEUES, s1_multi_tris_per_thread=2),
 ]
 
 
@@ -115,7 +117,8 @@ def test_options_do_not_change_results(opts):
             assert_vis_equal(api.as_uint64(v2), O.rasterize(t.meshes, t.views[0]), f"tiny {seed} with {opts}")
 
 
-@pytest.mark.parametrize("mode,tpt", [(0, 2), (0, 1), (0, 4), (1, 2), (2, 4), (3, 1), (3, 2), (3, 4)])
+@pytest.mark.parametrize("mode,tpt", [(0, 2), (0, 1), (0, 4), (1, 2), (2, 4), (3, 1), (3, 2), (3, 4), (2, 8), (4, 2),
+                                      (4, 8)])
 def test_instanced_stage1_modes(mode, tpt):
     """Instanced meshes take the first stage-1 launch (the vertex-sharing kernel with LDS
     deduplication in mode 3), at every multi-draw batch size."""
@@ -208,6 +211,9 @@ def _strip_scene(seed):
     dict(flags=api.FLAG_SINGLE_STRIPS, s1_draws_per_item=3), dict(s1_multi_tris_per_thread=8),
     dict(s1_multi_tris_per_thread=8, s1_block=64, s1_draws_per_item=5),
     dict(s1_multi_tris_per_thread=8, flags=api.FLAG_SINGLE_STRIPS, s1_tris_per_thread=8),
+    dict(s1_mode=4), dict(s1_mode=4, s1_multi_tris_per_thread=8), dict(s1_mode=4, flags=api.FLAG_NO_FAST_INTERIOR),
+    dict(s1_multi_tris_per_thread=8, s1_block=512, s1_draws_per_item=1),
+    dict(s1_multi_tris_per_thread=2, s1_draws_per_item=200, flags=api.FLAG_ZERO_QUEUES),
 ])
 def test_strips_and_interior_draws(opts):
     """The strip path (shared window positions and one union-box test per strip of 2, 4 or 8
@@ -225,7 +231,7 @@ def test_strips_and_interior_draws(opts):
 
 
 @pytest.mark.parametrize("opts", [dict(s1_block=96), dict(s1_tris_per_thread=3), dict(s1_multi_tris_per_thread=16),
-                                  dict(s1_mode=3, s1_multi_tris_per_thread=8), dict(s1_mode=4),
+                                  dict(s1_mode=3, s1_multi_tris_per_thread=8), dict(s1_mode=5),
                                   dict(s1_blocks_per_cu=65537), dict(small_px=65537),
                                   dict(q2_capacity=(1 << 30) + 1)])
 def test_invalid_options_are_rejected(opts):
