@@ -530,6 +530,26 @@ def run_resolve_bwd(args, api, torch, W):
     bwd = ev[1].elapsed_time(ev[2]) / reps
     covered_px = int(covered.sum().item())
     ctx.close()
+    # the fp32 atomic ceiling on this part for the same scatter: torch's index_add_ (one fp32 atomic
+    # add per element) of as many rows of 3 values as the backward adds, at seeded random rows of
+    # arrays of the backward's size
+    n_rows = g.attrs.shape[0]
+    rows = torch.randint(0, n_rows, (6 * covered_px,), device="cuda",
+                         generator=torch.Generator(device="cuda").manual_seed(58))
+    src = torch.ones((rows.numel(), 3), dtype=torch.float32, device="cuda")
+    dst = torch.zeros((n_rows, 3), dtype=torch.float32, device="cuda")
+    dst.index_add_(0, rows, src)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        dst.index_add_(0, rows, src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    probe_ms = ev[0].elapsed_time(ev[1]) / reps
+    probe = {"atomics": 3 * rows.numel(), "ms": round(probe_ms, 4),
+             "atomics_per_s": round(3 * rows.numel() / (probe_ms * 1e-3), 1),
+             "what": "torch index_add_ of 3-float rows at seeded random rows of a [V][3] fp32 array"}
+    del rows, src, dst
     px = view.width * view.height
     nbytes = backward_bytes(px, covered_px)
     ach = nbytes / (bwd * 1e-3) / 1e9
@@ -539,7 +559,8 @@ def run_resolve_bwd(args, api, torch, W):
             "roofline": {"kernel": "resolve_backward_kernel", "bound": "hbm", "achieved": round(ach, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
                          "traffic": None, "algorithmic_bytes": nbytes, "launch_ms": round(bwd, 4),
-                         "fp32_atomics": atomics, "atomics_per_s": round(atomics / (bwd * 1e-3), 1)}}
+                         "fp32_atomics": atomics, "atomics_per_s": round(atomics / (bwd * 1e-3), 1)},
+            "atomic_probe": probe}
 
 
 def host_info() -> dict:

@@ -402,52 +402,116 @@ __global__ void __launch_bounds__(256) resolve_screen_kernel(ScreenArgs a)
 //   dL/da_k = g b_k;  G_k = g . a_k;  dL/dq_j = (G_j - sum_k G_k b_k) / s;
 //   dL/dlambda_j = dL/dq_j zI_j;  dL/dw_j = -(dL/dq_j lambda_j) zI_j^2;
 //   lambda_0 = d1 x d2, lambda_1 = d2 x d0, lambda_2 = d0 x d1 with d_k = s_k - pixel centre.
+//
+// Workgroups take 16 x 16 pixel tiles: neighbouring pixels reach neighbouring vertices of a dense
+// mesh, so the atomics a workgroup issues close together in time fall on fewer cache lines.  The
+// atomics themselves are performed at the memory side, one request per cache-line sector and
+// instruction, so each wavefront stages the rows its 64 pixels add to (3 vertices x (C + 3) values)
+// in LDS and issues them with neighbouring lanes on neighbouring components of one row: the three
+// adds of a row then travel as one request instead of three (C <= kBwdStageC; more channels take
+// one atomic per lane and value).
+constexpr uint32_t kBwdStageC = 4;
+
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __global__ void __launch_bounds__(256) resolve_backward_kernel(ScreenArgs a)
 {
-    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= (uint64_t)a.W * (uint64_t)a.H) return;
-    uint32_t vi[3];
-    if (!screen_tri(a, p, vi)) return;
-    const double cx = (double)(p % (uint64_t)a.W) + 0.5, cy = (double)(p / (uint64_t)a.W) + 0.5;
-    double d[3][2], zI[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        d[k][0] = (double)a.pos_ss[3 * (size_t)vi[k]] - cx;
-        d[k][1] = (double)a.pos_ss[3 * (size_t)vi[k] + 1] - cy;
-        zI[k] = 1.0 / (double)a.pos_ss[3 * (size_t)vi[k] + 2];
-    }
-    const double lam[3] = {d[1][0] * d[2][1] - d[1][1] * d[2][0], d[2][0] * d[0][1] - d[2][1] * d[0][0],
-                           d[0][0] * d[1][1] - d[0][1] * d[1][0]};
-    const double q[3] = {lam[0] * zI[0], lam[1] * zI[1], lam[2] * zI[2]};
-    const double sum = q[0] + q[1] + q[2];
-    const double b[3] = {q[0] / sum, q[1] / sum, q[2] / sum};
-    const float* g = a.grad_out + p * a.C;
-    double G[3] = {0.0, 0.0, 0.0};
-    for (uint32_t c = 0; c < a.C; ++c) {
-        const double gc = g[c];
+    __shared__ uint32_t s_vid[4][192];
+    __shared__ float s_att[4][192 * kBwdStageC];
+    __shared__ float s_pos[4][192 * 3];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const bool staged = a.C <= kBwdStageC;
+    const uint32_t tiles_x = ((uint32_t)a.W + 15u) / 16u;
+    const uint32_t x = (blockIdx.x % tiles_x) * 16u + (threadIdx.x & 15u);
+    const uint32_t y = (blockIdx.x / tiles_x) * 16u + (threadIdx.x >> 4);
+    const uint64_t p = (uint64_t)y * (uint64_t)a.W + x;
+    uint32_t vi[3] = {~0u, ~0u, ~0u};
+    const bool have = x < (uint32_t)a.W && y < (uint32_t)a.H && screen_tri(a, p, vi);
+    double d[3][2] = {}, zI[3] = {}, lam[3] = {}, b[3] = {}, G[3] = {0.0, 0.0, 0.0};
+    double inv_sum = 0.0;
+    if (have) {
+        const double cx = (double)x + 0.5, cy = (double)y + 0.5;
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            G[k] += gc * (double)a.attrs[(size_t)vi[k] * a.C + c];
-            unsafeAtomicAdd(a.grad_attr + (size_t)vi[k] * a.C + c, (float)(gc * b[k]));
+            d[k][0] = (double)a.pos_ss[3 * (size_t)vi[k]] - cx;
+            d[k][1] = (double)a.pos_ss[3 * (size_t)vi[k] + 1] - cy;
+            zI[k] = 1.0 / (double)a.pos_ss[3 * (size_t)vi[k] + 2];
+        }
+        lam[0] = d[1][0] * d[2][1] - d[1][1] * d[2][0];
+        lam[1] = d[2][0] * d[0][1] - d[2][1] * d[0][0];
+        lam[2] = d[0][0] * d[1][1] - d[0][1] * d[1][0];
+        const double q[3] = {lam[0] * zI[0], lam[1] * zI[1], lam[2] * zI[2]};
+        inv_sum = 1.0 / (q[0] + q[1] + q[2]);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) b[k] = q[k] * inv_sum;
+    }
+    // attribute gradients g b_k, and G_k = g . a_k
+    const float* g = a.grad_out + (have ? p : 0) * a.C;
+    for (uint32_t c = 0; c < a.C; ++c) {
+        const double gc = have ? (double)g[c] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (have) G[k] += gc * (double)a.attrs[(size_t)vi[k] * a.C + c];
+            const float v = (float)(gc * b[k]);
+            if (staged) s_att[wave][(3 * lane + k) * a.C + c] = v;
+            else if (have) unsafeAtomicAdd(a.grad_attr + (size_t)vi[k] * a.C + c, v);
         }
     }
-    if (!a.grad_pos) return;
-    const double Gb = G[0] * b[0] + G[1] * b[1] + G[2] * b[2];
-    double L[3], dw[3];
+    // position gradients
+    float gpos[3][3] = {};
+    if (a.grad_pos && have) {
+        const double Gb = G[0] * b[0] + G[1] * b[1] + G[2] * b[2];
+        double L[3], dw[3];
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const double Q = (G[j] - Gb) / sum;
-        L[j] = Q * zI[j];
-        dw[j] = -(Q * lam[j]) * zI[j] * zI[j];
+        for (int j = 0; j < 3; ++j) {
+            const double Q = (G[j] - Gb) * inv_sum;
+            L[j] = Q * zI[j];
+            dw[j] = -(Q * lam[j]) * zI[j] * zI[j];
+        }
+        const double gx[3] = {L[2] * d[1][1] - L[1] * d[2][1], L[0] * d[2][1] - L[2] * d[0][1],
+                              L[1] * d[0][1] - L[0] * d[1][1]};
+        const double gy[3] = {L[1] * d[2][0] - L[2] * d[1][0], L[2] * d[0][0] - L[0] * d[2][0],
+                              L[0] * d[1][0] - L[1] * d[0][0]};
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            gpos[k][0] = (float)gx[k];
+            gpos[k][1] = (float)gy[k];
+            gpos[k][2] = (float)dw[k];
+        }
     }
-    const double gx[3] = {L[2] * d[1][1] - L[1] * d[2][1], L[0] * d[2][1] - L[2] * d[0][1], L[1] * d[0][1] - L[0] * d[1][1]};
-    const double gy[3] = {L[1] * d[2][0] - L[2] * d[1][0], L[2] * d[0][0] - L[0] * d[2][0], L[0] * d[1][0] - L[1] * d[0][0]};
+    if (!staged) {
+        if (a.grad_pos && have)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+#pragma unroll
+                for (int j = 0; j < 3; ++j) unsafeAtomicAdd(a.grad_pos + 3 * (size_t)vi[k] + j, gpos[k][j]);
+        return;
+    }
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        unsafeAtomicAdd(a.grad_pos + 3 * (size_t)vi[k] + 0, (float)gx[k]);
-        unsafeAtomicAdd(a.grad_pos + 3 * (size_t)vi[k] + 1, (float)gy[k]);
-        unsafeAtomicAdd(a.grad_pos + 3 * (size_t)vi[k] + 2, (float)dw[k]);
+        s_vid[wave][3 * lane + k] = have ? vi[k] : ~0u;
+#pragma unroll
+        for (int j = 0; j < 3; ++j) s_pos[wave][(3 * lane + k) * 3 + j] = gpos[k][j];
     }
+    wave_sync();
+    // item it = (row, component) in row-major order, row = 3 lane + k of the staging lane
+    const uint32_t n_att = 192u * a.C;
+    for (uint32_t it = lane; it < n_att; it += 64u) {
+        const uint32_t row = it / a.C;
+        const uint32_t v = s_vid[wave][row];
+        if (v != ~0u) unsafeAtomicAdd(a.grad_attr + (size_t)v * a.C + (it - row * a.C), s_att[wave][it]);
+    }
+    if (a.grad_pos)
+        for (uint32_t it = lane; it < 576u; it += 64u) {
+            const uint32_t row = it / 3u;
+            const uint32_t v = s_vid[wave][row];
+            if (v != ~0u) unsafeAtomicAdd(a.grad_pos + 3 * (size_t)v + (it - 3u * row), s_pos[wave][it]);
+        }
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -508,7 +572,8 @@ hipError_t launch_resolve_screen(const ScreenArgs& a, hipStream_t s)
 
 hipError_t launch_resolve_backward(const ScreenArgs& a, hipStream_t s)
 {
-    resolve_backward_kernel<<<blocks_for((uint64_t)a.W * (uint64_t)a.H), 256, 0, s>>>(a);
+    const uint32_t tiles = (((uint32_t)a.W + 15u) / 16u) * (((uint32_t)a.H + 15u) / 16u);
+    resolve_backward_kernel<<<tiles, 256, 0, s>>>(a);
     return hipGetLastError();
 }
 
