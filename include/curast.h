@@ -83,6 +83,12 @@ typedef enum {
                                             positions per draw) */
 #define CURAST_FLAG_SINGLE_STRIPS 0x200u /* stage 1: detect triangle strips in the launch over
                                             single-draw meshes too */
+#define CURAST_FLAG_S1_OVERLAP    0x400u /* stage 1: run the launch over single-draw meshes on a
+                                            second stream of the context next to the launch over
+                                            multi-draw meshes (forked from and joined back into the
+                                            caller's stream, also under graph capture); stage times
+                                            then report the multi-draw launch's span as stage1_multi
+                                            and the rest of stage 1 as stage1_single */
 #define CURAST_FLAG_ZERO_QUEUES   0x80000000u /* testing aid: run with stage queues of capacity 0, so
                                                  every forwarded triangle takes the overflow paths */
 

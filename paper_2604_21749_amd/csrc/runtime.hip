@@ -98,6 +98,10 @@ struct curast_ctx {
     uint32_t* q3_binned = nullptr;
     uint32_t tiles_alloc = 0;
     hipStream_t capture_stream = nullptr;
+    // the second stream of the overlapped stage-1 launches, and the events that fork it from the
+    // caller's stream and join it back
+    hipStream_t side_stream = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
     std::vector<GraphEntry> graphs;
     std::vector<TimedFrame> timed;
     std::vector<hipEvent_t> event_pool;   // timing events of collected frames, reused by later frames
@@ -731,25 +735,42 @@ int launch_frame(curast_ctx* ctx, const RasterArgs& a, uint64_t total_pixels, ui
         // launches fewer workgroups (one per item measured slower on the HBM-bound launch)
         const uint32_t mode = ctx->opt.s1_mode, blk = ctx->opt.s1_block;
         const uint32_t grid_cap = (uint32_t)std::min<uint64_t>((uint64_t)cus * ctx->opt.s1_blocks_per_cu, 1ull << 24);
-        auto launch_part = [&](uint32_t part, uint32_t tpt, uint32_t grid) {
+        auto launch_part = [&](uint32_t part, uint32_t tpt, uint32_t grid, hipStream_t st) {
             grid = std::min(grid, grid_cap);
             RasterArgs a1 = a;
             a1.part = part;
-            if (part == 1 && mode == 3) return launch_stage1_share(a1, tpt, stats, grid, s);
-            if (mode == 1) return launch_stage1(a1, blk, tpt, stats, grid, s);
+            if (part == 1 && mode == 3) return launch_stage1_share(a1, tpt, stats, grid, st);
+            if (mode == 1) return launch_stage1(a1, blk, tpt, stats, grid, st);
             const bool strips = !(a.flags & kFlagNoStrips) && tpt >= 2 &&
                                 (part == 1 || (a.flags & kFlagSingleStrips));
             // strip spheres in the multi-draw launch, s1_mode 0 and 2 (s1_mode 4: union boxes only)
             const bool spheres = strips && part == 1 && mode != 4;
-            return launch_stage1_fast(a1, blk, tpt, strips, spheres, stats, grid, s);
+            return launch_stage1_fast(a1, blk, tpt, strips, spheres, stats, grid, st);
         };
-        if (grid_share) {
-            e = launch_part(1, ctx->opt.s1_multi_tris_per_thread, grid_share);
+        if (grid_share && (a.flags & kFlagS1Overlap)) {
+            // the single-draw launch (bound by memory) on the side stream next to the multi-draw one
+            // (bound by the vector ALUs), so that the two share the compute units; both only append
+            // to the queues and take atomic minima, so the result does not depend on their order
+            e = hipEventRecord(ctx->fork_ev, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(ctx->side_stream, ctx->fork_ev, 0);
+            if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 stream fork");
+            e = launch_part(2, ctx->opt.s1_tris_per_thread, std::max<uint32_t>(grid1, 1), ctx->side_stream);
+            if (e == hipSuccess) e = hipEventRecord(ctx->join_ev, ctx->side_stream);
+            if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 kernel launch");
+            e = launch_part(1, ctx->opt.s1_multi_tris_per_thread, grid_share, s);
             if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 kernel launch (multi-draw meshes)");
+            if (tf) hipEventRecord(tf->ev[2], s);
+            e = hipStreamWaitEvent(s, ctx->join_ev, 0);
+            if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 stream join");
+        } else {
+            if (grid_share) {
+                e = launch_part(1, ctx->opt.s1_multi_tris_per_thread, grid_share, s);
+                if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 kernel launch (multi-draw meshes)");
+            }
+            if (tf) hipEventRecord(tf->ev[2], s);
+            e = launch_part(2, ctx->opt.s1_tris_per_thread, std::max<uint32_t>(grid1, 1), s);
+            if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 kernel launch");
         }
-        if (tf) hipEventRecord(tf->ev[2], s);
-        e = launch_part(2, ctx->opt.s1_tris_per_thread, std::max<uint32_t>(grid1, 1));
-        if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 kernel launch");
     }
     if (tf) hipEventRecord(tf->ev[3], s);
     e = launch_stage1_overflow(a, cus * 4, s);
@@ -1126,6 +1147,9 @@ int curast_create(const curast_options* opt, curast_ctx** out)
     if (hipMemset(ctx->counters, 0, sizeof(unsigned long long) * kNumCounters) != hipSuccess) return cleanup(CURAST_E_HIP);
     if (hipMemset(ctx->stats, 0, sizeof(unsigned long long) * kNumStats) != hipSuccess) return cleanup(CURAST_E_HIP);
     if (hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking) != hipSuccess) return cleanup(CURAST_E_HIP);
+    if (hipStreamCreateWithFlags(&ctx->side_stream, hipStreamNonBlocking) != hipSuccess) return cleanup(CURAST_E_HIP);
+    if (hipEventCreateWithFlags(&ctx->fork_ev, hipEventDisableTiming) != hipSuccess) return cleanup(CURAST_E_HIP);
+    if (hipEventCreateWithFlags(&ctx->join_ev, hipEventDisableTiming) != hipSuccess) return cleanup(CURAST_E_HIP);
     if (hipEventCreateWithFlags(&ctx->raster_stage.ev, hipEventDisableTiming) != hipSuccess) return cleanup(CURAST_E_HIP);
     if (hipEventCreateWithFlags(&ctx->resolve_stage.ev, hipEventDisableTiming) != hipSuccess) return cleanup(CURAST_E_HIP);
     if (ensure_queues(ctx)) return cleanup(CURAST_E_OOM);
@@ -1162,6 +1186,9 @@ int curast_destroy(curast_ctx* ctx)
     if (ctx->stats) hipFree(ctx->stats);
     if (ctx->ranges) hipFree(ctx->ranges);
     if (ctx->capture_stream) hipStreamDestroy(ctx->capture_stream);
+    if (ctx->side_stream) hipStreamDestroy(ctx->side_stream);
+    if (ctx->fork_ev) hipEventDestroy(ctx->fork_ev);
+    if (ctx->join_ev) hipEventDestroy(ctx->join_ev);
     delete ctx;
     return CURAST_OK;
 }
