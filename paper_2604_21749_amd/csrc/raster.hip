@@ -925,13 +925,15 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                         for (uint32_t j = 0; j < dn; ++j) {
                             const uint32_t d = dc + j;
                             const DrawDesc& D = d_draws[d];
-                            const ViewDesc V = d_views[D.view & kDrawViewMask];
+                            // the view word with the sphere test's fields: one batch of scalar loads per draw
+                            const SphereDraw sd = sphere_draw(d_draws, d);
                             bool pass;
-                            if (D.view & kDrawInterior) {
+                            if (sd.view & kDrawInterior) {
                                 // the strip's bounding sphere first (see sphere_reject)
-                                pass = any_valid && !sphere_reject(sphere_draw(d_draws, d), sc, sr, tiny_cull);
+                                pass = any_valid && !sphere_reject(sd, sc, sr, tiny_cull);
                                 if (any_valid && pass) st.add(kStSpherePass);
                             } else {
+                                const ViewDesc V = d_views[D.view & kDrawViewMask];
                                 // the box around the strip's TPT + 2 window positions holds each triangle's box
                                 auto body = [&](auto tag) {
                                     constexpr bool INTERIOR = decltype(tag)::value;
