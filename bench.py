@@ -338,13 +338,14 @@ def read_profile(path: str, src_path: str, src_key: str = ""):
 
 
 RASTER_SRC = os.path.join(ROOT, "paper_2604_21749_amd", "csrc", "raster.hip")
+RESOLVE_SRC = os.path.join(ROOT, "paper_2604_21749_amd", "csrc", "resolve.hip")
 
 
-def read_traffic(kernel: str, path: str = "", src_path: str = ""):
+def read_traffic(kernel: str, path: str = "", src_path: str = "", src_key: str = "raster.hip"):
     """HBM bytes per launch of a kernel from the committed profiler summary, if it was taken from
     the current kernel source (else None)."""
     f = read_profile(path or os.path.join(ROOT, "profiles", "stage1_c3_traffic.txt"), src_path or RASTER_SRC,
-                     "raster.hip")
+                     src_key)
     v = (f or {}).get(f"{kernel} hbm bytes per launch")
     return int(v) if v else None
 
@@ -558,7 +559,9 @@ def run_resolve_bwd(args, api, torch, W):
             "resolve_bwd_ms": round(bwd, 4),
             "roofline": {"kernel": "resolve_backward_kernel", "bound": "hbm", "achieved": round(ach, 1),
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                         "traffic": None, "algorithmic_bytes": nbytes, "launch_ms": round(bwd, 4),
+                         "traffic": read_traffic("resolve_backward_kernel", os.path.join(ROOT, "profiles",
+                                                 "resolve_backward_c5.txt"), RESOLVE_SRC, "resolve.hip"),
+                         "algorithmic_bytes": nbytes, "launch_ms": round(bwd, 4),
                          "fp32_atomics": atomics, "atomics_per_s": round(atomics / (bwd * 1e-3), 1)},
             "atomic_probe": probe}
 
