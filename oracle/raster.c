@@ -485,8 +485,13 @@ int orc_coverage_counts(const orc_mesh* meshes, uint32_t M, const orc_view* view
             draw_matrix(view->vp, meshes[m].inst ? meshes[m].inst + 12 * (size_t)i : NULL, A);
             for (uint64_t t = 0; t < meshes[m].T; ++t) {
                 cvert c[3];
-                for (int k = 0; k < 3; ++k)
-                    c[k] = transform(A, meshes[m].pos + 3 * (uint64_t)meshes[m].idx[3 * t + (uint64_t)k]);
+                int bad = 0;
+                for (int k = 0; k < 3; ++k) {
+                    const uint32_t vi = meshes[m].idx[3 * t + (uint64_t)k];
+                    if (vi >= meshes[m].V) bad = 1;     /* out-of-range index: no fragments (R14) */
+                    else c[k] = transform(A, meshes[m].pos + 3 * (uint64_t)vi);
+                }
+                if (bad) continue;
                 if (c[0].w < vc.near_plane && c[1].w < vc.near_plane && c[2].w < vc.near_plane) continue;
                 cvert poly[8];
                 int nv;
