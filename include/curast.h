@@ -92,6 +92,11 @@ typedef enum {
 #define CURAST_FLAG_ZERO_QUEUES   0x80000000u /* testing aid: run with stage queues of capacity 0, so
                                                  every forwarded triangle takes the overflow paths */
 
+/* Host logging: with CURAST_LOG set in the environment to a value other than "0" (read once per
+   process), the library prints one "[curast] ..." line to stderr for each context set-up, frame
+   plan (meshes, views, draws kept and culled, work items), graph capture, autotuner result and
+   error; unset, it prints nothing. */
+
 /* Tuning knobs; 0 selects the default (or the autotuned value).  None of them changes results. */
 typedef struct {
     uint32_t small_px;          /* stage-1 limit on pixel centres in the clamped bbox (default 32; the

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/curast.h"
+#include "log.h"
 
 extern "C" int curast_internal_queue_counts(curast_ctx* ctx, uint64_t out[3]);
 extern "C" int curast_internal_num_cus(const curast_ctx* ctx);
@@ -148,6 +149,7 @@ extern "C" int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint3
             std::fclose(f);
             if (hit) {
                 o.flags = keep_flags;
+                curast::log_line("autotune: cached options for %s", key.c_str());
                 rc = curast_set_options(ctx, &o);
                 if (rc == CURAST_OK && chosen) curast_get_options(ctx, chosen);
                 return rc;
@@ -227,6 +229,7 @@ extern "C" int curast_autotune(curast_ctx* ctx, const curast_mesh* meshes, uint3
     best.flags = keep_flags;
     rc = curast_set_options(ctx, &best);
     if (rc) return rc;
+    curast::log_line("autotune: %s -> %.4f ms: %s", key.c_str(), best_ms, to_json(key, best).c_str());
     if (chosen) curast_get_options(ctx, chosen);
     if (cache_path) {
         if (FILE* f = std::fopen(cache_path, "a")) {

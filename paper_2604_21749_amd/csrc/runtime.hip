@@ -21,6 +21,7 @@
 
 #include "../../include/curast.h"
 #include "common.h"
+#include "log.h"
 
 namespace curast {
 hipError_t launch_clear(const RasterArgs& a, uint32_t grid, hipStream_t s);
@@ -116,6 +117,7 @@ namespace {
 
 int fail(curast_ctx* ctx, int code, const std::string& msg)
 {
+    log_line("error %d: %s", code, msg.c_str());
     if (ctx) ctx->err = msg;
     return code;
 }
@@ -123,8 +125,23 @@ int fail(curast_ctx* ctx, int code, const std::string& msg)
 int hip_fail(curast_ctx* ctx, hipError_t e, const char* what)
 {
     std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    log_line("error %d: %s", CURAST_E_HIP, m.c_str());
     if (ctx) ctx->err = m;
     return CURAST_E_HIP;
+}
+
+// One log line describing a frame's plan (CURAST_LOG).
+template <class PlanType>
+void log_plan(const char* what, const PlanType& P, uint32_t M, uint32_t n_views)
+{
+    if (!log_on()) return;
+    size_t interior = 0;
+    for (const auto& D : P.draws) interior += (D.view & kDrawInterior) ? 1 : 0;
+    log_line("%s: %u meshes, %u views, %zu draws (%zu interior, %llu culled), %llu work items (%llu multi-draw), "
+             "%llu triangle x draw items, %llu pixels",
+             what, M, n_views, (size_t)P.draws.size(), interior, (unsigned long long)P.draws_culled,
+             (unsigned long long)P.hdr.total_batches, (unsigned long long)P.hdr.shared_batches,
+             (unsigned long long)P.tri_draws, (unsigned long long)P.total_pixels);
 }
 
 #define HIP_TRY(ctx, expr)                                  \
@@ -808,6 +825,7 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
     if (rc) return rc;
     write_plan(P, ctx->raster_stage.host);
     ctx->draws_culled += P.draws_culled;
+    log_plan(use_graph ? "batched frame" : "frame", P, M, n_views);
     TimedFrame* tf = begin_timing(ctx);
     if (!use_graph) {
         HIP_TRY(ctx, hipMemcpyAsync(ctx->raster_stage.dev, ctx->raster_stage.host, P.bytes, hipMemcpyHostToDevice, s));
@@ -857,6 +875,7 @@ int rasterize_impl(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const
             return hip_fail(ctx, e, "hipGraphInstantiate");
         }
         ctx->graphs.push_back(g);
+        log_line("captured a frame graph (%zu held by the context)", ctx->graphs.size());
         ge = &ctx->graphs.back();
     }
     if (tf) HIP_TRY(ctx, hipEventRecord(tf->ev[0], s));
@@ -1159,6 +1178,11 @@ int curast_create(const curast_options* opt, curast_ctx** out)
         fprintf(stderr, "curast_create: hipGetSymbolAddress(scratch) failed: %s\n", hipGetErrorString(se));
         return cleanup(CURAST_E_HIP);
     }
+    log_line("context on device %d (%d CUs): s1_mode %u, s1_block %u, tris/lane %u/%u (single/multi), draws/item %u, "
+             "small_px %u, medium_px %u, queues %u/%u/%u, flags 0x%x",
+             ctx->device, ctx->cus, ctx->opt.s1_mode, ctx->opt.s1_block, ctx->opt.s1_tris_per_thread,
+             ctx->opt.s1_multi_tris_per_thread, ctx->opt.s1_draws_per_item, ctx->opt.small_px, ctx->opt.medium_px,
+             ctx->opt.q2_capacity, ctx->opt.large_capacity, ctx->opt.q3_capacity, ctx->opt.flags);
     *out = ctx;
     return CURAST_OK;
 }
@@ -1618,6 +1642,7 @@ int curast_plan(const curast_mesh* meshes, uint32_t M, const curast_view* views,
     Plan P;
     int rc = build_plan(nullptr, o, meshes, M, views, n_views, P, visible);
     if (rc) return rc;
+    log_plan("plan", P, M, n_views);
     if (bases) {
         int64_t n = curast_id_bases(meshes, M, bases);
         if (n < 0) return (int)n;

@@ -230,3 +230,28 @@ def test_prescaled_interior_needs_a_small_error_bound(api):
         assert visible[0, 0] == expect, (origin, visible)
         visible, _, _ = api.plan([_cpu_mesh(api, m)], [view], flags=api.FLAG_NO_FAST_INTERIOR)
         assert visible[0, 0] == 1
+
+
+def test_host_log_lines(api):
+    """CURAST_LOG=1 prints the plan of a frame and every error to stderr (host only; a separate
+    process, since the setting is read once)."""
+    code = r'''
+import numpy as np, torch
+from paper_2604_21749_amd import api, workloads as W
+s = W.random_tiny_scene(1)
+m = api.GpuMesh(torch.from_numpy(s.meshes[0].pos), torch.from_numpy(s.meshes[0].idx.view(np.int32)),
+                s.meshes[0].inst, s.meshes[0].bsphere)
+api.plan([m], [s.views[0]])
+try:
+    api.plan([m], [W.View(s.views[0].vp, 0.0, 8, 8)])
+except api.CurastError:
+    pass
+'''
+    env = dict(os.environ, CURAST_LOG="1", PYTHONPATH=ROOT)
+    r = subprocess.run([os.sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
+    assert r.returncode == 0, r.stderr[-2000:]
+    assert re.search(r"^\[curast\] plan: 1 meshes, 1 views, \d+ draws", r.stderr, flags=re.M), r.stderr
+    assert "[curast] error -1: near plane must be finite and > 0" in r.stderr, r.stderr
+    env["CURAST_LOG"] = "0"
+    r = subprocess.run([os.sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=ROOT)
+    assert r.returncode == 0 and "[curast]" not in r.stderr
