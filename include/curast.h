@@ -390,6 +390,28 @@ int curast_resolve_backward(curast_ctx* ctx, const uint64_t* visbuffer, int32_t 
                             const float* grad_out, float* grad_attr, float* grad_pos, void* stream);
 
 /*
+ * Backward of curast_resolve (the multi-mesh, multi-instance resolve of Sec. 4.4) with visibility
+ * held fixed: for every covered pixel of view->visbuffer, the pixel's (mesh, instance) and
+ * triangle are found as in the forward, its vertices projected with the same fp32 operations, and
+ * grad_out [H][W][C] is scattered through the barycentrics (the chain rule of
+ * curast_resolve_backward, fp64 per pixel, each contribution rounded once to fp32).
+ *   attrs       host [M] array of device [V_m][C] attribute pointers (as curast_resolve);
+ *   grad_out    device [H][W][C];
+ *   grad_attrs  host [M] array of device [V_m][C] pointers, ACCUMULATED (the caller zeroes them);
+ *               the instances of a mesh add into its one set of rows; a NULL entry skips mesh m;
+ *   grad_pos    NULL, or host [M] array of device [V_m][3] pointers or NULL entries, ACCUMULATED:
+ *               gradients to the unsnapped window positions (sx, sy, w) that curast_project gives
+ *               for mesh m's only instance (a non-NULL entry for a mesh with several instances is
+ *               CURAST_E_INVALID).
+ * Float atomics: the accumulation order is not deterministic.  Errors: CURAST_E_INVALID (NULL
+ * pointers, C outside [1, 16], a bad view or mesh), CURAST_E_ID_RANGE, CURAST_E_HIP.
+ */
+int curast_resolve_backward_meshes(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M,
+                                   const curast_view* view, const float* const* attrs, uint32_t C,
+                                   const float* grad_out, float* const* grad_attrs,
+                                   float* const* grad_pos, void* stream);
+
+/*
  * Pick stage thresholds, workgroup sizes, work-item sizes and queue capacities for this scene
  * by timing candidates with HIP events (coordinate descent over a fixed grid, Sec. 4's
  * "experimentally determined" thresholds made automatic).  Results never change outputs.

@@ -102,6 +102,7 @@ SIGNATURES = {
                                         _P, C.c_uint32, _P, _P]),
     "curast_resolve_backward": (C.c_int, [_P, _P, C.c_int32, C.c_int32, _P, C.c_uint64, C.c_uint64, _P,
                                           C.c_uint32, _P, C.c_uint32, _P, _P, _P, _P]),
+    "curast_resolve_backward_meshes": (C.c_int, [_P, _P, C.c_uint32, _P, _P, C.c_uint32, _P, _P, _P, _P]),
     "curast_autotune": (C.c_int, [_P, _P, C.c_uint32, _P, C.c_uint32, C.c_char_p, C.POINTER(Options), _P]),
     "curast_get_stats": (C.c_int, [_P, C.POINTER(StatsStruct)]),
     "curast_reset_stats": (C.c_int, [_P]),
@@ -565,6 +566,47 @@ class Context:
         self._check(lib().curast_resolve_backward(
             self._h, vis.data_ptr(), W, H, indices.data_ptr(), indices.shape[0], int(id_base), pos_ss.data_ptr(),
             pos_ss.shape[0], attrs.data_ptr(), Cn, grad_out.data_ptr(), grad_attr.data_ptr(), _ptr(grad_pos),
+            _stream(vis.device)))
+
+    def resolve_backward_meshes(self, meshes: Sequence[GpuMesh], view, vis: torch.Tensor,
+                                attrs: Sequence[torch.Tensor], grad_out: torch.Tensor,
+                                grad_attrs: Sequence[Optional[torch.Tensor]],
+                                grad_pos: Optional[Sequence[Optional[torch.Tensor]]] = None):
+        """curast_resolve_backward_meshes: backward of resolve() over every (mesh, instance);
+        accumulates into grad_attrs[m] [V_m, C] and, for one-instance meshes, grad_pos[m] [V_m, 3]
+        (gradients to the window positions project() gives)."""
+        keep = []
+        arr = (MeshStruct * max(1, len(meshes)))(*[_mesh_struct(m, keep) for m in meshes])
+        Cn = int(attrs[0].shape[1])
+        for m, a in zip(meshes, attrs):
+            _check_cuda(a, torch.float32, "attrs", Cn)
+            if a.shape[0] != m.num_vertices:
+                raise ValueError("attrs[m] must have one row per vertex of mesh m")
+        _check_cuda(vis, torch.int64, "visbuffer")
+        _check_cuda(grad_out, torch.float32, "grad_out")
+        if tuple(grad_out.shape) != (view.height, view.width, Cn) or tuple(vis.shape) != (view.height, view.width):
+            raise ValueError("vis must be [H, W] and grad_out [H, W, C] of the view")
+        if len(attrs) != len(meshes) or len(grad_attrs) != len(meshes) or (
+                grad_pos is not None and len(grad_pos) != len(meshes)):
+            raise ValueError("one attrs, grad_attrs (and grad_pos) entry per mesh")
+        for m, g in zip(meshes, grad_attrs):
+            if g is not None:
+                _check_cuda(g, torch.float32, "grad_attrs", Cn)
+                if g.shape[0] != m.num_vertices:
+                    raise ValueError("grad_attrs[m] must have one row per vertex of mesh m")
+        if grad_pos is not None:
+            for m, g in zip(meshes, grad_pos):
+                if g is not None:
+                    _check_cuda(g, torch.float32, "grad_pos", 3)
+                    if g.shape[0] != m.num_vertices:
+                        raise ValueError("grad_pos[m] must have one row per vertex of mesh m")
+        n = max(1, len(meshes))
+        aptr = (C.c_void_p * n)(*[a.data_ptr() for a in attrs])
+        gaptr = (C.c_void_p * n)(*[_ptr(g) for g in grad_attrs])
+        gpptr = None if grad_pos is None else (C.c_void_p * n)(*[_ptr(g) for g in grad_pos])
+        vs = _view_struct(view.vp, view.near, view.width, view.height, vis)
+        self._check(lib().curast_resolve_backward_meshes(
+            self._h, arr, len(meshes), C.byref(vs), aptr, Cn, grad_out.data_ptr(), gaptr, gpptr,
             _stream(vis.device)))
 
     # -- tuning, statistics, timing ---------------------------------------------------------------

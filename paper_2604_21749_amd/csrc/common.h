@@ -176,6 +176,9 @@ struct ResolveArgs {
     float* out;                   // [H][W][C], or [H/ss][W/ss][C] when supersampled
     uint32_t ss;                  // samples per axis and output pixel (1: no supersampling)
     const TexDesc* tex;           // [M] textures of the textured resolve (attrs are then the UVs)
+    const float* grad_out;        // backward input [H][W][C]
+    float* const* grad_attrs;     // [M] per-mesh attribute gradients [V][C] (accumulated), entries may be null
+    float* const* grad_pos;       // [M] per-mesh window-position gradients [V][3], or null (one-instance meshes)
 };
 
 struct ScreenArgs {

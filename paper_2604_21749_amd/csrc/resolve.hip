@@ -412,6 +412,58 @@ __global__ void __launch_bounds__(256) resolve_screen_kernel(ScreenArgs a)
 // one atomic per lane and value).
 constexpr uint32_t kBwdStageC = 4;
 
+// The fp64 terms of one pixel's chain rule, from the fp32 window positions (sx, sy, w) of its
+// triangle's vertices and the pixel (x, y).
+struct BwdTerms {
+    double d[3][2];   // pixel-relative positions
+    double zI[3];
+    double lam[3];
+    double b[3];
+    double inv_sum;   // 1 / (q0 + q1 + q2)
+};
+
+__device__ __forceinline__ void bwd_terms(const float (&sx)[3], const float (&sy)[3], const float (&w)[3], uint32_t x,
+                                          uint32_t y, BwdTerms& t)
+{
+    const double cx = (double)x + 0.5, cy = (double)y + 0.5;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        t.d[k][0] = (double)sx[k] - cx;
+        t.d[k][1] = (double)sy[k] - cy;
+        t.zI[k] = 1.0 / (double)w[k];
+    }
+    t.lam[0] = t.d[1][0] * t.d[2][1] - t.d[1][1] * t.d[2][0];
+    t.lam[1] = t.d[2][0] * t.d[0][1] - t.d[2][1] * t.d[0][0];
+    t.lam[2] = t.d[0][0] * t.d[1][1] - t.d[0][1] * t.d[1][0];
+    const double q[3] = {t.lam[0] * t.zI[0], t.lam[1] * t.zI[1], t.lam[2] * t.zI[2]};
+    t.inv_sum = 1.0 / (q[0] + q[1] + q[2]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) t.b[k] = q[k] * t.inv_sum;
+}
+
+// Gradients to (sx, sy, w) of the three vertices from G_k = g . a_k, each rounded once to fp32.
+__device__ __forceinline__ void bwd_pos(const BwdTerms& t, const double (&G)[3], float (&gpos)[3][3])
+{
+    const double Gb = G[0] * t.b[0] + G[1] * t.b[1] + G[2] * t.b[2];
+    double L[3], dw[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const double Q = (G[j] - Gb) * t.inv_sum;
+        L[j] = Q * t.zI[j];
+        dw[j] = -(Q * t.lam[j]) * t.zI[j] * t.zI[j];
+    }
+    const double gx[3] = {L[2] * t.d[1][1] - L[1] * t.d[2][1], L[0] * t.d[2][1] - L[2] * t.d[0][1],
+                          L[1] * t.d[0][1] - L[0] * t.d[1][1]};
+    const double gy[3] = {L[1] * t.d[2][0] - L[2] * t.d[1][0], L[2] * t.d[0][0] - L[0] * t.d[2][0],
+                          L[0] * t.d[1][0] - L[1] * t.d[0][0]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        gpos[k][0] = (float)gx[k];
+        gpos[k][1] = (float)gy[k];
+        gpos[k][2] = (float)dw[k];
+    }
+}
+
 __device__ __forceinline__ void wave_sync()
 {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -432,23 +484,17 @@ __global__ void __launch_bounds__(256) resolve_backward_kernel(ScreenArgs a)
     const uint64_t p = (uint64_t)y * (uint64_t)a.W + x;
     uint32_t vi[3] = {~0u, ~0u, ~0u};
     const bool have = x < (uint32_t)a.W && y < (uint32_t)a.H && screen_tri(a, p, vi);
-    double d[3][2] = {}, zI[3] = {}, lam[3] = {}, b[3] = {}, G[3] = {0.0, 0.0, 0.0};
-    double inv_sum = 0.0;
+    BwdTerms t = {};
+    double G[3] = {0.0, 0.0, 0.0};
     if (have) {
-        const double cx = (double)x + 0.5, cy = (double)y + 0.5;
+        float sx[3], sy[3], w[3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
-            d[k][0] = (double)a.pos_ss[3 * (size_t)vi[k]] - cx;
-            d[k][1] = (double)a.pos_ss[3 * (size_t)vi[k] + 1] - cy;
-            zI[k] = 1.0 / (double)a.pos_ss[3 * (size_t)vi[k] + 2];
+            sx[k] = a.pos_ss[3 * (size_t)vi[k]];
+            sy[k] = a.pos_ss[3 * (size_t)vi[k] + 1];
+            w[k] = a.pos_ss[3 * (size_t)vi[k] + 2];
         }
-        lam[0] = d[1][0] * d[2][1] - d[1][1] * d[2][0];
-        lam[1] = d[2][0] * d[0][1] - d[2][1] * d[0][0];
-        lam[2] = d[0][0] * d[1][1] - d[0][1] * d[1][0];
-        const double q[3] = {lam[0] * zI[0], lam[1] * zI[1], lam[2] * zI[2]};
-        inv_sum = 1.0 / (q[0] + q[1] + q[2]);
-#pragma unroll
-        for (int k = 0; k < 3; ++k) b[k] = q[k] * inv_sum;
+        bwd_terms(sx, sy, w, x, y, t);
     }
     // attribute gradients g b_k, and G_k = g . a_k
     const float* g = a.grad_out + (have ? p : 0) * a.C;
@@ -457,33 +503,14 @@ __global__ void __launch_bounds__(256) resolve_backward_kernel(ScreenArgs a)
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
             if (have) G[k] += gc * (double)a.attrs[(size_t)vi[k] * a.C + c];
-            const float v = (float)(gc * b[k]);
+            const float v = (float)(gc * t.b[k]);
             if (staged) s_att[wave][(3 * lane + k) * a.C + c] = v;
             else if (have) unsafeAtomicAdd(a.grad_attr + (size_t)vi[k] * a.C + c, v);
         }
     }
     // position gradients
     float gpos[3][3] = {};
-    if (a.grad_pos && have) {
-        const double Gb = G[0] * b[0] + G[1] * b[1] + G[2] * b[2];
-        double L[3], dw[3];
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            const double Q = (G[j] - Gb) * inv_sum;
-            L[j] = Q * zI[j];
-            dw[j] = -(Q * lam[j]) * zI[j] * zI[j];
-        }
-        const double gx[3] = {L[2] * d[1][1] - L[1] * d[2][1], L[0] * d[2][1] - L[2] * d[0][1],
-                              L[1] * d[0][1] - L[0] * d[1][1]};
-        const double gy[3] = {L[1] * d[2][0] - L[2] * d[1][0], L[2] * d[0][0] - L[0] * d[2][0],
-                              L[0] * d[1][0] - L[1] * d[0][0]};
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            gpos[k][0] = (float)gx[k];
-            gpos[k][1] = (float)gy[k];
-            gpos[k][2] = (float)dw[k];
-        }
-    }
+    if (a.grad_pos && have) bwd_pos(t, G, gpos);
     if (!staged) {
         if (a.grad_pos && have)
 #pragma unroll
@@ -512,6 +539,62 @@ __global__ void __launch_bounds__(256) resolve_backward_kernel(ScreenArgs a)
             const uint32_t v = s_vid[wave][row];
             if (v != ~0u) unsafeAtomicAdd(a.grad_pos + 3 * (size_t)v + (it - 3u * row), s_pos[wave][it]);
         }
+}
+
+// Backward of the multi-mesh resolve (resolve_kernel) with visibility held fixed: one lane per
+// pixel finds the (mesh, instance) and triangle as the forward does, projects its three vertices
+// with the same fp32 operations, and applies the chain rule above; attribute gradients of every
+// instance of a mesh add into the mesh's rows, position gradients (to the unsnapped window
+// positions of one-instance meshes) where the mesh has a gradient buffer.  One atomic per value.
+__global__ void __launch_bounds__(256) resolve_backward_meshes_kernel(ResolveArgs a, const uint64_t* __restrict__ bases,
+                                                                      const DrawDesc* __restrict__ pairs,
+                                                                      const MeshDesc* __restrict__ meshes,
+                                                                      const float* const* __restrict__ attrs)
+{
+    __shared__ uint64_t s_bases[kLdsBases + 1];
+    const uint64_t* B = stage_bases(a, bases, s_bases);
+    const uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (uint64_t)a.W * (uint64_t)a.H) return;
+    uint32_t pair, vi[3];
+    if (!pixel_triangle(a, B, pairs, meshes, p, pair, vi)) return;
+    const DrawDesc& D = pairs[pair];
+    const uint32_t m = D.mesh;
+    const MeshDesc& M = meshes[m];
+    float sx[3], sy[3], w[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        float q[3];
+        mesh_vertex(M, vi[k], q);
+        const Clip c = transform(D.A, q[0], q[1], q[2]);
+        const float zI = 1.0f / c.w;
+        sx[k] = __builtin_fmaf(c.x * zI, a.hW, a.hW);
+        sy[k] = __builtin_fmaf(c.y * zI, a.hH, a.hH);
+        w[k] = c.w;
+    }
+    const uint32_t x = (uint32_t)(p % (uint64_t)a.W), y = (uint32_t)(p / (uint64_t)a.W);
+    BwdTerms t;
+    bwd_terms(sx, sy, w, x, y, t);
+    const float* at = attrs[m];
+    float* ga = a.grad_attrs[m];
+    float* gp = a.grad_pos ? a.grad_pos[m] : nullptr;
+    const float* g = a.grad_out + p * a.C;
+    double G[3] = {0.0, 0.0, 0.0};
+    for (uint32_t c = 0; c < a.C; ++c) {
+        const double gc = (double)g[c];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            G[k] += gc * (double)at[(size_t)vi[k] * a.C + c];
+            if (ga) unsafeAtomicAdd(ga + (size_t)vi[k] * a.C + c, (float)(gc * t.b[k]));
+        }
+    }
+    if (gp) {
+        float gpos[3][3];
+        bwd_pos(t, G, gpos);
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) unsafeAtomicAdd(gp + 3 * (size_t)vi[k] + j, gpos[k][j]);
+    }
 }
 
 // ----------------------------------------------------------------------------------------------
@@ -574,6 +657,13 @@ hipError_t launch_resolve_backward(const ScreenArgs& a, hipStream_t s)
 {
     const uint32_t tiles = (((uint32_t)a.W + 15u) / 16u) * (((uint32_t)a.H + 15u) / 16u);
     resolve_backward_kernel<<<tiles, 256, 0, s>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t launch_resolve_backward_meshes(const ResolveArgs& a, hipStream_t s)
+{
+    resolve_backward_meshes_kernel<<<blocks_for((uint64_t)a.W * (uint64_t)a.H), 256, 0, s>>>(a, a.bases, a.pairs,
+                                                                                             a.meshes, a.attrs);
     return hipGetLastError();
 }
 

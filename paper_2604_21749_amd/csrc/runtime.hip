@@ -44,6 +44,7 @@ hipError_t launch_resolve_textured(const ResolveArgs& a, hipStream_t s);
 hipError_t launch_build_mips(uint32_t* texels, uint32_t w, uint32_t h, uint32_t levels, hipStream_t s);
 hipError_t launch_resolve_screen(const ScreenArgs& a, hipStream_t s);
 hipError_t launch_resolve_backward(const ScreenArgs& a, hipStream_t s);
+hipError_t launch_resolve_backward_meshes(const ResolveArgs& a, hipStream_t s);
 }  // namespace curast
 
 using namespace curast;
@@ -1040,7 +1041,8 @@ void collect_timings(curast_ctx* ctx)
 }
 
 int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view& view,
-                       const float* const* attrs, const curast_texture* textures, ResolveArgs& a, size_t& bytes_out)
+                       const float* const* attrs, const curast_texture* textures, ResolveArgs& a, size_t& bytes_out,
+                       float* const* grad_attrs = nullptr, float* const* grad_pos = nullptr)
 {
     uint64_t np = 0;
     for (uint32_t m = 0; m < M; ++m) np += n_inst(meshes[m]);
@@ -1051,7 +1053,8 @@ int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, c
     const size_t off_meshes = align_up(off_pairs + sizeof(DrawDesc) * std::max<uint64_t>(np, 1), 256);
     const size_t off_attrs = align_up(off_meshes + sizeof(MeshDesc) * std::max<uint32_t>(M, 1), 256);
     const size_t off_tex = align_up(off_attrs + sizeof(float*) * std::max<uint32_t>(M, 1), 256);
-    const size_t bytes = textures ? align_up(off_tex + sizeof(TexDesc) * std::max<uint32_t>(M, 1), 256) : off_tex;
+    const size_t off_grad = textures ? align_up(off_tex + sizeof(TexDesc) * std::max<uint32_t>(M, 1), 256) : off_tex;
+    const size_t bytes = grad_attrs ? align_up(off_grad + 2 * sizeof(float*) * std::max<uint32_t>(M, 1), 256) : off_grad;
     int rc = ensure_staging(ctx, ctx->resolve_stage, bytes);
     if (rc) return rc;
     char* h = static_cast<char*>(ctx->resolve_stage.host);
@@ -1061,10 +1064,16 @@ int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, c
     MeshDesc* md = reinterpret_cast<MeshDesc*>(h + off_meshes);
     const float** ap = reinterpret_cast<const float**>(h + off_attrs);
     TexDesc* td = reinterpret_cast<TexDesc*>(h + off_tex);
+    float** gap = reinterpret_cast<float**>(h + off_grad);
+    float** gpp = gap + std::max<uint32_t>(M, 1);
     uint64_t base = 0, p = 0;
     for (uint32_t m = 0; m < M; ++m) {
         md[m] = mesh_desc(meshes[m]);
         ap[m] = attrs[m];
+        if (grad_attrs) {
+            gap[m] = grad_attrs[m];
+            gpp[m] = grad_pos ? grad_pos[m] : nullptr;
+        }
         bases[m] = base;
         mpair[m] = (uint32_t)p;
         if (textures) {
@@ -1101,6 +1110,8 @@ int build_resolve_desc(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, c
     a.meshes = reinterpret_cast<const MeshDesc*>(d + off_meshes);
     a.attrs = reinterpret_cast<const float* const*>(d + off_attrs);
     a.tex = textures ? reinterpret_cast<const TexDesc*>(d + off_tex) : nullptr;
+    a.grad_attrs = grad_attrs ? reinterpret_cast<float* const*>(d + off_grad) : nullptr;
+    a.grad_pos = grad_attrs && grad_pos ? reinterpret_cast<float* const*>(d + off_grad) + std::max<uint32_t>(M, 1) : nullptr;
     a.n_pairs = (uint32_t)np;
     a.n_meshes = M;
     bytes_out = bytes;
@@ -1568,6 +1579,47 @@ int curast_resolve_backward(curast_ctx* ctx, const uint64_t* visbuffer, int32_t 
     TimedFrame* tf = begin_timing(ctx);
     if (tf) hipEventRecord(tf->ev[7], s);
     HIP_TRY(ctx, launch_resolve_backward(a, s));
+    if (tf) {
+        hipEventRecord(tf->ev[8], s);
+        tf->used[kTResolveBwd] = 1;
+    }
+    return CURAST_OK;
+}
+
+int curast_resolve_backward_meshes(curast_ctx* ctx, const curast_mesh* meshes, uint32_t M, const curast_view* view,
+                                   const float* const* attrs, uint32_t C, const float* grad_out,
+                                   float* const* grad_attrs, float* const* grad_pos, void* stream)
+{
+    if (!ctx) return CURAST_E_INVALID;
+    if (!view || !grad_out || (M && (!meshes || !attrs || !grad_attrs)))
+        return fail(ctx, CURAST_E_INVALID, "NULL pointer argument");
+    if (C < 1 || C > 16) return fail(ctx, CURAST_E_INVALID, "C must lie in [1, 16]");
+    int rc = check_view(ctx, *view);
+    if (rc) return rc;
+    uint64_t total = 0;
+    for (uint32_t m = 0; m < M; ++m) {
+        rc = check_mesh(ctx, meshes[m]);
+        if (rc) return rc;
+        if (meshes[m].num_triangles && !attrs[m]) return fail(ctx, CURAST_E_INVALID, "attrs[m] is NULL");
+        if (grad_pos && grad_pos[m] && n_inst(meshes[m]) != 1)
+            return fail(ctx, CURAST_E_INVALID, "position gradients only for meshes with one instance");
+        total += meshes[m].num_triangles * (uint64_t)n_inst(meshes[m]);
+        if (total > kMaxIds) return fail(ctx, CURAST_E_ID_RANGE, "more than 2^36 triangle instances");
+    }
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    ResolveArgs a{};
+    size_t bytes = 0;
+    rc = build_resolve_desc(ctx, meshes, M, *view, attrs, nullptr, a, bytes, grad_attrs, grad_pos);
+    if (rc) return rc;
+    a.C = C;
+    a.grad_out = grad_out;
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->resolve_stage.dev, ctx->resolve_stage.host, bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(ctx, hipEventRecord(ctx->resolve_stage.ev, s));
+    ctx->resolve_stage.pending = true;
+    TimedFrame* tf = begin_timing(ctx);
+    if (tf) hipEventRecord(tf->ev[7], s);
+    HIP_TRY(ctx, launch_resolve_backward_meshes(a, s));
     if (tf) {
         hipEventRecord(tf->ev[8], s);
         tf->used[kTResolveBwd] = 1;
