@@ -205,9 +205,10 @@ def config_summary(h, rooflines) -> dict:
             "unique_triangles": int(sum(m.num_triangles for m in scene.meshes)),
             "triangle_instances": int(scene.total_tri_instances),
             "triangle_instances_after_cull": int(h["visible"]),
-            "ms_per_frame": round(h["ms"], 4), "ms_per_frame_without_stage_events": round(h["ms_no_events"], 4),
-            "gtris_s": round(h["visible"] / (h["ms"] * 1e-3) / 1e9, 4),
-            "frame_events_ms": h["frame_events"], "stage_ms": {k: round(v, 4) for k, v in h["stage_ms"].items()},
+            "ms_per_frame": round(h["ms_no_events"], 4), "ms_per_frame_with_stage_events": round(h["ms"], 4),
+            "gtris_s": round(h["visible"] / (h["ms_no_events"] * 1e-3) / 1e9, 4),
+            "frame_events_ms": h["frame_events_no_events"],
+            "stage_ms": {k: round(v, 4) for k, v in h["stage_ms"].items()},
             "roofline": rooflines[0], "roofline_other_stage1_launch": rooflines[1],
             "options": ("autotuned: " if h["autotuned"] else "library defaults: ") +
                        json.dumps({k: v for k, v in h["options"].items() if k != "flags"}),
@@ -723,12 +724,12 @@ def main():
     head = config_summary(h, (rl_main, rl_other))
     result = {
         "metric": METRIC,
-        "value": round(h["visible"] / (h["ms"] * 1e-3) / 1e9, 4),
+        "value": round(h["visible"] / (h["ms_no_events"] * 1e-3) / 1e9, 4),
         "unit": "Gtris/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(h["ms"], 4),
+        "ms_per_step": round(h["ms_no_events"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -741,12 +742,12 @@ def main():
             "triangle_instances_after_cull": head["triangle_instances_after_cull"],
             "frame": "clear + stages 1-3 + resolve (RGB)", "options": head["options"],
         },
-        "ms_per_step_without_stage_events": head["ms_per_frame_without_stage_events"],
+        "ms_per_step_with_stage_events": head["ms_per_frame_with_stage_events"],
         "stage_ms": head["stage_ms"],
-        "frame_events_ms": h["frame_events"],
+        "frame_events_ms": h["frame_events_no_events"],
         "roofline": rl_main,
         "roofline_other_stage1_launch": rl_other,
-        "gtris_s_submitted": round(scene.total_tri_instances / (h["ms"] * 1e-3) / 1e9, 4),
+        "gtris_s_submitted": round(scene.total_tri_instances / (h["ms_no_events"] * 1e-3) / 1e9, 4),
         "supersampling": h["supersampling"],
         "compressed": h["compressed"],
         "textured_resolve": h["textured"],
