@@ -53,12 +53,14 @@ __device__ __forceinline__ uint32_t window_bits(uint32_t w0, uint32_t w1, uint32
     return __builtin_amdgcn_alignbit(hi, lo, s & 31);
 }
 
-__device__ __forceinline__ void packed_triangle(const MeshDesc& M, uint64_t t, uint32_t (&v)[3])
+// The three indices whose bits start at bit offset (uword words + lbit bits) of the stream:
+// uword is the same for the whole wavefront (64-bit address arithmetic once per wavefront),
+// lbit < 2^32 is the lane's part.
+__device__ __forceinline__ void packed_triangle_at(const MeshDesc& M, uint64_t uword, uint32_t lbit, uint32_t (&v)[3])
 {
     const uint32_t b = M.idx_bits;
-    const uint64_t bit = 3 * t * (uint64_t)b;
-    const CURAST_GLOBAL uint32_t* w = gl(M.idx) + (bit >> 5);
-    const uint32_t o = (uint32_t)bit & 31;
+    const CURAST_GLOBAL uint32_t* w = gl(M.idx) + uword + (lbit >> 5);
+    const uint32_t o = lbit & 31;
     uint32_t w0, w1, w2 = 0, w3 = 0;
     if (b <= 11) {                            // o + 3 b <= 64: two words
         const u32x2_a4 d = *(const CURAST_GLOBAL u32x2_a4*)w;
@@ -74,6 +76,12 @@ __device__ __forceinline__ void packed_triangle(const MeshDesc& M, uint64_t t, u
     const uint32_t mask = b >= 32 ? 0xFFFFFFFFu : ((1u << b) - 1u);
 #pragma unroll
     for (int k = 0; k < 3; ++k) v[k] = M.idx_min + (window_bits(w0, w1, w2, w3, o + k * b) & mask);
+}
+
+__device__ __forceinline__ void packed_triangle(const MeshDesc& M, uint64_t t, uint32_t (&v)[3])
+{
+    const uint64_t bit = 3 * t * (uint64_t)M.idx_bits;
+    packed_triangle_at(M, bit >> 5, (uint32_t)bit & 31u, v);
 }
 
 // Vertex indices of triangle t (CMP: the mesh is known to be compressed; otherwise decided per
@@ -96,7 +104,18 @@ template <int CMP = -1>
 __device__ __forceinline__ void mesh_vertex(const MeshDesc& M, uint32_t v, float (&p)[3])
 {
     const bool packed = CMP < 0 ? M.qpos != nullptr : CMP != 0;
-    if (packed) {
+    if (CMP == 1) {
+        // the launches specialized for compressed meshes take meshes of at most 2^29 vertices (the
+        // host checks), so byte offsets stay below 2^32: 32-bit offset arithmetic from the mesh's
+        // base address, the same load and decode as below
+        const uint32_t e = 3u * v;
+        const u32x2_a4 d =
+            *(const CURAST_GLOBAL u32x2_a4*)((const CURAST_GLOBAL char*)gl(M.qpos) + (uint32_t)((e >> 1) << 2));
+        const uint64_t q = ((uint64_t)d.x | ((uint64_t)d.y << 32)) >> ((e & 1u) * 16u);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+            p[c] = __builtin_fmaf((float)(uint32_t)((q >> (16 * c)) & 0xFFFFu), M.step[c], M.lo[c]);
+    } else if (packed) {
         const uint64_t e = 3 * (uint64_t)v;   // first element; the load starts at element e & ~1
         const u32x2_a4 d = *(const CURAST_GLOBAL u32x2_a4*)((const CURAST_GLOBAL uint32_t*)gl(M.qpos) + (e >> 1));
         const uint64_t q = ((uint64_t)d.x | ((uint64_t)d.y << 32)) >> ((e & 1) * 16);

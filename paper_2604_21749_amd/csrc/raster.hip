@@ -853,13 +853,22 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
         uint32_t vi[TPT][3];
         bool valid[TPT];
         uint32_t tri[TPT];
+        // compressed indices: the bit offset of the work item's first triangle once per wavefront
+        // (64-bit), the lane's triangles relative to it (32-bit); an invalid lane reads the item's
+        // first triangle, which exists
+        const uint64_t t0 = tb * (uint64_t)(BLOCK * TPT);
+        const uint64_t ubit = CMP == 1 ? 3u * t0 * (uint64_t)mesh.idx_bits : 0u;
 #pragma unroll
         for (int k = 0; k < TPT; ++k) {
-            const uint64_t t = tb * (uint64_t)(BLOCK * TPT) +
-                               (STRIPS ? (uint64_t)(threadIdx.x * TPT + k) : (uint64_t)(k * BLOCK + threadIdx.x));
+            const uint32_t j = STRIPS ? threadIdx.x * TPT + k : k * BLOCK + threadIdx.x;
+            const uint64_t t = t0 + j;
             tri[k] = (uint32_t)t;
             valid[k] = t < mesh.T;
-            mesh_triangle<CMP>(mesh, valid[k] ? t : 0, vi[k]);
+            if constexpr (CMP == 1)
+                packed_triangle_at(mesh, ubit >> 5, (uint32_t)(ubit & 31u) + (valid[k] ? 3u * j * mesh.idx_bits : 0u),
+                                   vi[k]);
+            else
+                mesh_triangle<CMP>(mesh, valid[k] ? t : 0, vi[k]);
         }
 #pragma unroll
         for (int k = 0; k < TPT; ++k)

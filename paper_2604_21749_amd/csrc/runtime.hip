@@ -637,7 +637,8 @@ int build_plan(curast_ctx* ctx, const curast_options& o, const curast_mesh* mesh
             const uint32_t dc = mesh_draw_count[m];
             if (!dc || !meshes[m].num_triangles || shared_mesh(m) != (pass == 0)) continue;
             any_cmp |= meshes[m].compressed != nullptr;
-            all_cmp &= meshes[m].compressed != nullptr;
+            // the all-compressed kernels use 32-bit offsets into the quantized positions
+            all_cmp &= meshes[m].compressed != nullptr && meshes[m].num_vertices <= (1u << 29);
             Segment sg{};
             sg.batch_begin = P.hdr.total_batches;
             sg.mesh = m;
