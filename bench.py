@@ -321,32 +321,40 @@ def run_textured(args, api, torch, W, ctx, gm, attrs, view, vis):
     return res
 
 
-def read_profile(path: str, src_path: str, src_key: str = ""):
+def read_profile(path: str, src_path: str, src_key: str = "", runtime_path: str = ""):
     """Fields of a committed profiler summary ('key: value' lines), if it was taken from the current
-    kernel source (its recorded sha256 prefix matches), else None: the counters no longer describe
+    kernel source (its recorded sha256 prefix matches) and, where it records one, from the current
+    host runtime (which sets each launch's options), else None: the counters no longer describe
     the kernel."""
     import hashlib
     if not os.path.exists(path):
         return None
-    sha = hashlib.sha256(open(src_path, "rb").read()).hexdigest()[:16]
+    sha = lambda p: hashlib.sha256(open(p, "rb").read()).hexdigest()[:16]
     fields = {}
     for line in open(path):
         if ":" in line and not line.startswith("#"):
             k, v = line.rsplit(":", 1)          # keys may hold a colon ("sha256[:16]"), values do not
             fields[k.strip()] = v.strip()
     src = src_key or os.path.basename(src_path)
-    return fields if fields.get(f"{src} sha256[:16]") == sha else None
+    if fields.get(f"{src} sha256[:16]") != sha(src_path):
+        return None
+    rt = fields.get("runtime.hip sha256[:16]")
+    if rt is not None and rt != sha(runtime_path or RUNTIME_SRC):
+        return None
+    return fields
 
 
 RASTER_SRC = os.path.join(ROOT, "paper_2604_21749_amd", "csrc", "raster.hip")
 RESOLVE_SRC = os.path.join(ROOT, "paper_2604_21749_amd", "csrc", "resolve.hip")
+RUNTIME_SRC = os.path.join(ROOT, "paper_2604_21749_amd", "csrc", "runtime.hip")
 
 
-def read_traffic(kernel: str, path: str = "", src_path: str = "", src_key: str = "raster.hip"):
+def read_traffic(kernel: str, path: str = "", src_path: str = "", src_key: str = "raster.hip",
+                 runtime_path: str = ""):
     """HBM bytes per launch of a kernel from the committed profiler summary, if it was taken from
-    the current kernel source (else None)."""
+    the current kernel source and runtime (else None)."""
     f = read_profile(path or os.path.join(ROOT, "profiles", "stage1_c3_traffic.txt"), src_path or RASTER_SRC,
-                     src_key)
+                     src_key, runtime_path)
     v = (f or {}).get(f"{kernel} hbm bytes per launch")
     return int(v) if v else None
 

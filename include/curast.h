@@ -69,7 +69,8 @@ typedef enum {
 /* Option flags. */
 #define CURAST_FLAG_NO_TINY_CULL  0x1u  /* keep triangles whose bbox holds no pixel centre
                                            (result unchanged; Sec. 4.1, Table 4) */
-#define CURAST_FLAG_NO_EARLY_OUT  0x2u  /* always issue the atomic even if the stored key is smaller */
+#define CURAST_FLAG_NO_EARLY_OUT  0x2u  /* always issue the atomic, in every stage, even if the stored
+                                           key is smaller (see CURAST_FLAG_EARLY_OUT_ALL) */
 #define CURAST_FLAG_NO_MESH_CULL  0x4u  /* skip the host bounding-sphere frustum cull */
 #define CURAST_FLAG_STATS         0x8u  /* count per-stage events (slower; read with curast_get_stats) */
 #define CURAST_FLAG_NO_GRAPH      0x10u /* batched calls launch kernels directly instead of a hipGraph */
@@ -89,6 +90,14 @@ typedef enum {
                                             caller's stream, also under graph capture); stage times
                                             then report the multi-draw launch's span as stage1_multi
                                             and the rest of stage 1 as stage1_single */
+#define CURAST_FLAG_EARLY_OUT_ALL 0x800u /* read the stored key before each atomic minimum and skip the
+                                            atomic when the key is not smaller, in every stage; by
+                                            default only the stage-1 launch over single-draw meshes,
+                                            stage 3 and the overflow passes read first, while the
+                                            stage-1 launch over multi-draw meshes and stage 2 issue
+                                            the atomic directly as the paper does (Sec. 4.1), which
+                                            measured faster there; CURAST_FLAG_NO_EARLY_OUT, when
+                                            also set, wins (no stage reads first) */
 #define CURAST_FLAG_ZERO_QUEUES   0x80000000u /* testing aid: run with stage queues of capacity 0, so
                                                  every forwarded triangle takes the overflow paths */
 

@@ -32,6 +32,7 @@ FLAG_NO_FAST_INTERIOR = 0x80
 FLAG_NO_STRIPS = 0x100
 FLAG_SINGLE_STRIPS = 0x200
 FLAG_S1_OVERLAP = 0x400
+FLAG_EARLY_OUT_ALL = 0x800
 FLAG_ZERO_QUEUES = 0x80000000
 
 EMPTY_KEY = np.uint64(0xFFFFFFFFFFFFFFFF)

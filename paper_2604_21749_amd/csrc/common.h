@@ -127,6 +127,7 @@ constexpr uint32_t kFlagNoFastInterior = 0x80u;     // no prescaled interior dra
 constexpr uint32_t kFlagNoStrips = 0x100u;          // no triangle strips in stage 1
 constexpr uint32_t kFlagSingleStrips = 0x200u;      // strips in the single-draw stage-1 launch too
 constexpr uint32_t kFlagS1Overlap = 0x400u;         // the two stage-1 launches on two streams at once
+constexpr uint32_t kFlagEarlyOutAll = 0x800u;       // read the stored key before the atomic in every stage
 constexpr uint32_t kFlagZeroQueues = 0x80000000u;   // testing aid: queue capacities of zero
 
 struct RasterArgs {

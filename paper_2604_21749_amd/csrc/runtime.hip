@@ -758,6 +758,10 @@ int launch_frame(curast_ctx* ctx, const RasterArgs& a, uint64_t total_pixels, ui
             grid = std::min(grid, grid_cap);
             RasterArgs a1 = a;
             a1.part = part;
+            // the multi-draw launch writes with the atomic alone: its fragments come from small
+            // instanced triangles, and a read before each atomic cost a memory round trip per
+            // fragment there; the single-draw launch, bound by memory, gains from skipping atomics
+            if (part == 1 && !(a.flags & kFlagEarlyOutAll)) a1.flags |= kFlagNoEarlyOut;
             if (part == 1 && mode == 3) return launch_stage1_share(a1, tpt, stats, grid, st);
             if (mode == 1) return launch_stage1(a1, blk, tpt, stats, grid, st);
             const bool strips = !(a.flags & kFlagNoStrips) && tpt >= 2 &&
@@ -795,7 +799,12 @@ int launch_frame(curast_ctx* ctx, const RasterArgs& a, uint64_t total_pixels, ui
     e = launch_stage1_overflow(a, cus * 4, s);
     if (e != hipSuccess) return hip_fail(ctx, e, "stage-1 overflow kernel launch");
     if (tf) hipEventRecord(tf->ev[4], s);
-    e = launch_stage2(a, std::max<uint32_t>(1, ctx->opt.s2_waves / 4), stats, s);
+    {
+        // stage 2 writes with the atomic alone as well (see the stage-1 launches)
+        RasterArgs a2 = a;
+        if (!(a.flags & kFlagEarlyOutAll)) a2.flags |= kFlagNoEarlyOut;
+        e = launch_stage2(a2, std::max<uint32_t>(1, ctx->opt.s2_waves / 4), stats, s);
+    }
     if (e != hipSuccess) return hip_fail(ctx, e, "stage-2 kernel launch");
     if (tf) hipEventRecord(tf->ev[5], s);
     e = (a.flags & kFlagS3PerPart) ? launch_stage3(a, std::max<uint32_t>(1, ctx->opt.s3_blocks), stats, s)

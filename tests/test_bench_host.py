@@ -33,6 +33,20 @@ def test_traffic_is_read_only_for_the_profiled_kernel_source(tmp_path):
     assert b.read_traffic(k, str(tmp_path / "missing.txt"), str(src)) is None
 
 
+def test_traffic_recorded_with_a_runtime_sha_needs_that_runtime(tmp_path):
+    b = _bench()
+    src, rt = tmp_path / "k.hip", tmp_path / "runtime.hip"
+    src.write_bytes(b"__global__ void k() {}\n")
+    rt.write_bytes(b"void launch() {}\n")
+    sha = lambda p: hashlib.sha256(p.read_bytes()).hexdigest()[:16]
+    prof = tmp_path / "traffic.txt"
+    prof.write_text(f"raster.hip sha256[:16]: {sha(src)}\nruntime.hip sha256[:16]: {sha(rt)}\n"
+                    "kern hbm bytes per launch: 77\n")
+    assert b.read_traffic("kern", str(prof), str(src), runtime_path=str(rt)) == 77
+    rt.write_bytes(b"void launch() { /* other launch options */ }\n")
+    assert b.read_traffic("kern", str(prof), str(src), runtime_path=str(rt)) is None
+
+
 def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)

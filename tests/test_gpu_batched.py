@@ -72,7 +72,7 @@ def test_batched_under_the_option_sweep(opts):
 @pytest.mark.parametrize("opts", [{}, dict(flags=api.FLAG_ZERO_QUEUES), dict(flags=api.FLAG_S3_PER_PART),
                                   dict(flags=api.FLAG_ZERO_QUEUES | api.FLAG_S3_PER_PART, small_px=1, medium_px=1),
                                   dict(s1_multi_tris_per_thread=8, s1_draws_per_item=3),
-                                  dict(flags=api.FLAG_S1_OVERLAP)])
+                                  dict(flags=api.FLAG_S1_OVERLAP), dict(flags=api.FLAG_EARLY_OUT_ALL)])
 def test_batched_graph_replays(opts):
     """Three replays of one captured graph per scene, with new cameras (same structure) and eager
     work (fills, a plain frame) between them: every replay equals the oracle."""

@@ -42,7 +42,8 @@ def _instanced_sphere(n_inst=6, seed=3):
 @pytest.mark.parametrize("opts", [{}, dict(s1_mode=1), dict(s1_multi_tris_per_thread=8),
                                   dict(s1_multi_tris_per_thread=2, flags=api.FLAG_SINGLE_STRIPS),
                                   dict(s1_mode=3), dict(flags=api.FLAG_ZERO_QUEUES),
-                                  dict(flags=api.FLAG_S1_OVERLAP), dict(s1_mode=1, flags=api.FLAG_S1_OVERLAP)])
+                                  dict(flags=api.FLAG_S1_OVERLAP), dict(s1_mode=1, flags=api.FLAG_S1_OVERLAP),
+                                  dict(flags=api.FLAG_EARLY_OUT_ALL)])
 def test_out_of_range_indices_produce_nothing(opts):
     """R14 on every stage-1 kernel: the single-draw launch (C1 sphere and ground quad), the
     multi-draw launch with strips (an instanced sphere: broken indices split strips), the

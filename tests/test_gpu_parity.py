@@ -100,6 +100,8 @@ OPTION_SWEEP = [
     dict(flags=api.FLAG_S1_OVERLAP), dict(flags=api.FLAG_S1_OVERLAP | api.FLAG_ZERO_QUEUES, s1_mode=4),
     dict(flags=api.FLAG_S1_OVERLAP | api.FLAG_STATS | api.FLAG_TIMING, s1_mode=3),
     dict(s1_blocks_per_cu=3, s1_mode=3), dict(s1_blocks_per_cu=65536),
+    dict(flags=api.FLAG_EARLY_OUT_ALL), dict(flags=api.FLAG_EARLY_OUT_ALL | api.FLAG_NO_EARLY_OUT, s1_mode=3),
+    dict(flags=api.FLAG_EARLY_OUT_ALL | api.FLAG_ZERO_QUEUES, s1_multi_tris_per_thread=8),
     dict(s1_mode=4), dict(s1_mode=4, s1_multi_tris_per_thread=8), dict(s1_mode=2, s1_multi_tris_per_thread=8, s1_block=256),
     dict(s1_mode=4, flags=api.FLAG_ZERO_QUEUES, s1_multi_tris_per_thread=2),
 ]
