@@ -187,11 +187,9 @@ typedef struct {
 typedef struct {
     uint64_t tri_draws;         /* triangle x instance x view items submitted after the mesh cull */
     uint64_t draws_culled;      /* (mesh, instance, view) draws removed by the host cull */
-    uint64_t culled_near;       /* all three vertices behind the near plane (exact stage-1 path) */
-    uint64_t culled_frustum;    /* all vertices outside one side of the view (exact stage-1 path) */
-    uint64_t culled_tiny;       /* bbox holds no pixel centre (Sec. 4.1, Table 4); with s1_mode other
-                                   than 1 this also counts the near and side rejections of the fast
-                                   stage-1 tests, which run before the exact path */
+    uint64_t culled_near;       /* all three vertices behind the near plane */
+    uint64_t culled_frustum;    /* all vertices outside one side of the view */
+    uint64_t culled_tiny;       /* bbox holds no pixel centre (Sec. 4.1, Table 4) */
     uint64_t culled_backface;   /* snapped area <= 0 */
     uint64_t s1_rasterized;     /* triangles rasterized in stage 1 */
     uint64_t q2_entries;        /* triangles forwarded to stage 2 (high-water mark of the queue) */

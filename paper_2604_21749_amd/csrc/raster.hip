@@ -382,22 +382,11 @@ __global__ void __launch_bounds__(BLOCK) stage1_kernel(RasterArgs a, CURAST_DESC
 constexpr float kFastMargin = 1.0f / 32.0f;
 constexpr float kFastGuard = 2.0f;
 
-// Clip-plane bits of a vertex: 1 x > w, 2 x < -w, 4 y > w, 8 y < -w, 16 w < near.  A bit that all
-// three vertices of a triangle share puts the whole triangle (the convex hull of its clip-space
-// vertices) outside the view or in front of the near plane, the exact tests of the stage-1
-// classification.
-__device__ __forceinline__ uint32_t clip_bits(const Clip& c, float near_plane)
-{
-    return (uint32_t)(c.x > c.w) | (uint32_t)(c.x < -c.w) << 1 | (uint32_t)(c.y > c.w) << 2 |
-           (uint32_t)(c.y < -c.w) << 3 | (uint32_t)(c.w < near_plane) << 4;
-}
-
-// For a vertex outside the fast range, x is NaN and y carries its clip_bits (bit pattern).
 __device__ __forceinline__ float2 fast_window(const Clip& c, const ViewDesc& V)
 {
     const float g = kFastGuard * c.w;
     if (!(c.w >= V.near_plane) || !(c.w < 1e30f) || __builtin_fabsf(c.x) > g || __builtin_fabsf(c.y) > g)
-        return make_float2(__builtin_nanf(""), __builtin_bit_cast(float, clip_bits(c, V.near_plane)));
+        return make_float2(__builtin_nanf(""), 0.0f);
     const float r = __builtin_amdgcn_rcpf(c.w);
     return make_float2(__builtin_fmaf(c.x * r, V.hW, V.hW), __builtin_fmaf(c.y * r, V.hH, V.hH));
 }
@@ -443,22 +432,10 @@ __device__ __forceinline__ bool fast_reject_box(float2 a, float2 b, float2 c, co
                               fmaxf(a.y, fmaxf(b.y, c.y)), V, tiny_cull);
 }
 
-// Clip-plane bits of a fast_window output: exact for a vertex outside the fast range; for a finite
-// position only the bits its distance past a view border proves (the position is within
-// kFastMargin of the exact one, and w > 0, so past W means x > w).
-__device__ __forceinline__ uint32_t window_bits(float2 v, const ViewDesc& V)
-{
-    if (__builtin_isnan(v.x)) return __builtin_bit_cast(uint32_t, v.y);
-    return (uint32_t)(v.x > (V.wmax + 1.0f) + kFastMargin) | (uint32_t)(v.x < -kFastMargin) << 1 |
-           (uint32_t)(v.y > (V.hmax + 1.0f) + kFastMargin) << 2 | (uint32_t)(v.y < -kFastMargin) << 3;
-}
-
-// Same for the output of fast_window, whose x is NaN for a vertex outside the fast range: such a
-// triangle is rejected only when its vertices share a clip-plane bit.
+// Same for the output of fast_window, whose x is NaN for a vertex outside the fast range.
 __device__ __forceinline__ bool fast_reject(float2 a, float2 b, float2 c, const ViewDesc& V, bool tiny_cull)
 {
-    if (__builtin_isnan(a.x) | __builtin_isnan(b.x) | __builtin_isnan(c.x))
-        return (window_bits(a, V) & window_bits(b, V) & window_bits(c, V)) != 0u;
+    if (__builtin_isnan(a.x) | __builtin_isnan(b.x) | __builtin_isnan(c.x)) return false;
     return fast_reject_box(a, b, c, V, tiny_cull);
 }
 
@@ -630,20 +607,6 @@ __device__ __forceinline__ bool fast_reject_union(const float2 (&w)[N], const Vi
         y1 = fmaxf(y1, w[i].y);
     }
     return fast_reject_extent(x0, x1, y0, y1, V, tiny_cull);
-}
-
-// The union test of a strip's N fast_window outputs: the union box when all are finite, else a
-// clip-plane bit shared by all N vertices (every triangle of the strip then lies beyond it).
-template <int N>
-__device__ __forceinline__ bool fast_reject_strip(const float2 (&w)[N], bool any_nan, const ViewDesc& V, bool tiny_cull)
-{
-    if (any_nan) {
-        uint32_t bits = window_bits(w[0], V);
-#pragma unroll
-        for (int i = 1; i < N; ++i) bits &= window_bits(w[i], V);
-        return bits != 0u;
-    }
-    return fast_reject_union<N>(w, V, tiny_cull);
 }
 
 // Strip spheres.  Before a strip of an interior draw is projected vertex by vertex, it is tested
@@ -862,7 +825,7 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                                 : fast_window(transform(D.A, q0, q1, q2), V);
                 any_nan |= __builtin_isnan(w[i].x);
             }
-            const bool all_out = fast_reject_strip<NV>(w, any_nan, V, tiny_cull);
+            const bool all_out = !any_nan && fast_reject_union<NV>(w, V, tiny_cull);
             if (have) {
                 if (all_out) st.add(kStCulledTiny, TPT);
                 else st.add(kStStripPass);
@@ -990,7 +953,7 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                                         w[i] = window(tag, D, V, q[i]);
                                         if constexpr (!INTERIOR) any_nan |= __builtin_isnan(w[i].x);
                                     }
-                                    return fast_reject_strip<NV>(w, any_nan, V, tiny_cull);
+                                    return !any_nan && fast_reject_union<NV>(w, V, tiny_cull);
                                 };
                                 const bool all_out =
                                     (D.view & kDrawInterior) ? body(std::true_type{}) : body(std::false_type{});
@@ -1022,7 +985,7 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                                 w[i] = window(tag, D, V, q[i]);
                                 if constexpr (!INTERIOR) any_nan |= __builtin_isnan(w[i].x);
                             }
-                            const bool all_out = fast_reject_strip<TPT + 2>(w, any_nan, V, tiny_cull);
+                            const bool all_out = !any_nan && fast_reject_union<TPT + 2>(w, V, tiny_cull);
                             if (any_valid) {
                                 st.add(kStTriDraws, TPT);
                                 st.add(kStStripDraws);
