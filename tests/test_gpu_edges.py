@@ -139,3 +139,47 @@ def test_stage2_slivers_every_orientation(opts):
             total_s2 += c.stats()["s2_rasterized"]
             assert_vis_equal(api.as_uint64(vis), O.rasterize(s.meshes, s.views[0]), f"slivers seed {seed} {opts}")
         assert total_s2 > 50
+
+
+def _outside_scene():
+    """A 9 x 9 grid (128 triangles, consecutive ones forming strips) seen from a camera at the
+    origin looking down -z: instances wholly beyond each side of the view (|x| or |y| > 2w, so
+    the fast stage-1 tests have no window position for them), wholly behind the camera, in
+    front of it, crossing a side, and crossing the near plane; plus a one-instance copy beyond
+    the right side (the single-draw launch)."""
+    pos, idx = W.heightfield(9, 0.0, 1, shuffle=False)
+    # grid plane (x, z) -> (x, -z): facing the camera, x in [0, 1], y in [-1, 0] before the offset
+    face = np.array([[1, 0, 0], [0, 0, -1], [0, 1, 0]], np.float64)
+    flat = np.eye(3)
+    rows = [(face, (-0.5, 0.5, -3.0)),                  # in view
+            (face, (30.0, 0.5, -3.0)), (face, (-31.0, 0.5, -3.0)),      # beyond right / left
+            (face, (-0.5, 31.0, -3.0)), (face, (-0.5, -30.0, -3.0)),    # beyond top / bottom
+            (face, (-0.5, 0.5, 3.0)), (face, (-0.5, 0.5, -0.05)),       # behind, before the near plane
+            (face, (3.2, 0.5, -3.0)),                   # beyond the right side within 2w
+            (face, (1.8, 0.5, -3.0)),                   # across the right side
+            (flat, (-0.5, -0.05, -0.5))]                # across the near plane and w = 0
+    R = np.stack([r for r, _ in rows])
+    inst = W.instance_matrices(R, np.ones(len(rows)), np.array([t for _, t in rows]))
+    attrs = np.zeros((pos.shape[0], 3), np.float32)
+    multi = W.Mesh(pos, idx, inst=inst, attrs=attrs, bsphere=W.bounding_sphere(pos))
+    single = W.Mesh(pos, idx, inst=W.instance_matrices(face[None], np.ones(1), np.array([[40.0, 0.5, -3.0]])),
+                    attrs=attrs, bsphere=W.bounding_sphere(pos))
+    view = W.View(W.camera((0.0, 0.0, 0.0), (0.0, 0.0, -1.0), aspect=64 / 48), 0.1, 64, 48)
+    return [multi, single], view
+
+
+@pytest.mark.parametrize("mode", [1, 2, 3, 4])
+def test_triangles_beyond_a_clip_plane(mode):
+    """Triangles wholly beyond a side or the near plane, with vertices outside the fast stage-1
+    range (they take the exact path, which culls them: near and side culls are counted), next to
+    triangles across a side and across the near plane (rasterized, or clipped in stage 2): every
+    stage-1 mode's image equals the oracle's."""
+    meshes, view = _outside_scene()
+    ref = O.rasterize(meshes, view)
+    assert (ref != O.EMPTY).sum() > 100
+    with api.Context(flags=api.FLAG_STATS, s1_mode=mode, s1_multi_tris_per_thread=4) as c:
+        gm = [api.GpuMesh.from_host(m) for m in meshes]
+        vis = c.rasterize_meshes(gm, view)
+        assert_vis_equal(api.as_uint64(vis), ref, f"s1_mode {mode}")
+        st = c.stats()
+    assert st["culled_frustum"] > 0 and st["culled_near"] > 0, st
