@@ -189,7 +189,9 @@ typedef struct {
     uint64_t draws_culled;      /* (mesh, instance, view) draws removed by the host cull */
     uint64_t culled_near;       /* all three vertices behind the near plane */
     uint64_t culled_frustum;    /* all vertices outside one side of the view */
-    uint64_t culled_tiny;       /* bbox holds no pixel centre (Sec. 4.1, Table 4) */
+    uint64_t culled_tiny;       /* bbox holds no pixel centre (Sec. 4.1, Table 4); also the fast
+                                   stage-1 tests' rejections of triangles and strips wholly
+                                   beyond a side or the near plane */
     uint64_t culled_backface;   /* snapped area <= 0 */
     uint64_t s1_rasterized;     /* triangles rasterized in stage 1 */
     uint64_t q2_entries;        /* triangles forwarded to stage 2 (high-water mark of the queue) */

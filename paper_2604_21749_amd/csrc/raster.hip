@@ -382,11 +382,23 @@ __global__ void __launch_bounds__(BLOCK) stage1_kernel(RasterArgs a, CURAST_DESC
 constexpr float kFastMargin = 1.0f / 32.0f;
 constexpr float kFastGuard = 2.0f;
 
+// Clip-plane bits of a vertex: 1 x > w, 2 x < -w, 4 y > w, 8 y < -w, 16 w < near.  A bit that all
+// vertices of a strip share puts every triangle of it (the convex hull of its clip-space vertices)
+// outside the view or in front of the near plane: the exact near and side tests of the stage-1
+// classification.
+__device__ __forceinline__ uint32_t clip_bits(const Clip& c, float near_plane)
+{
+    return (uint32_t)(c.x > c.w) | (uint32_t)(c.x < -c.w) << 1 | (uint32_t)(c.y > c.w) << 2 |
+           (uint32_t)(c.y < -c.w) << 3 | (uint32_t)(c.w < near_plane) << 4;
+}
+
+// With BITS, the y of a vertex outside the fast range carries its clip_bits (bit pattern).
+template <bool BITS = false>
 __device__ __forceinline__ float2 fast_window(const Clip& c, const ViewDesc& V)
 {
     const float g = kFastGuard * c.w;
     if (!(c.w >= V.near_plane) || !(c.w < 1e30f) || __builtin_fabsf(c.x) > g || __builtin_fabsf(c.y) > g)
-        return make_float2(__builtin_nanf(""), 0.0f);
+        return make_float2(__builtin_nanf(""), BITS ? __builtin_bit_cast(float, clip_bits(c, V.near_plane)) : 0.0f);
     const float r = __builtin_amdgcn_rcpf(c.w);
     return make_float2(__builtin_fmaf(c.x * r, V.hW, V.hW), __builtin_fmaf(c.y * r, V.hH, V.hH));
 }
@@ -609,6 +621,33 @@ __device__ __forceinline__ bool fast_reject_union(const float2 (&w)[N], const Vi
     return fast_reject_extent(x0, x1, y0, y1, V, tiny_cull);
 }
 
+// Clip-plane bits of a fast_window<true> output: exact for a vertex outside the fast range; for a
+// finite position only the bits its distance past a view border proves (the position is within
+// kFastMargin of the exact one, and w > 0, so past W means x > w).
+__device__ __forceinline__ uint32_t window_bits(float2 v, const ViewDesc& V)
+{
+    if (__builtin_isnan(v.x)) return __builtin_bit_cast(uint32_t, v.y);
+    return (uint32_t)(v.x > (V.wmax + 1.0f) + kFastMargin) | (uint32_t)(v.x < -kFastMargin) << 1 |
+           (uint32_t)(v.y > (V.hmax + 1.0f) + kFastMargin) << 2 | (uint32_t)(v.y < -kFastMargin) << 3;
+}
+
+// The union test of a strip's N window positions; with BITS (positions from fast_window<true>) a
+// strip with a vertex outside the fast range is still rejected when all N vertices share a
+// clip-plane bit.
+template <int N, bool BITS>
+__device__ __forceinline__ bool fast_reject_strip(const float2 (&w)[N], bool any_nan, const ViewDesc& V, bool tiny_cull)
+{
+    if constexpr (BITS) {
+        if (any_nan) {
+            uint32_t bits = window_bits(w[0], V);
+#pragma unroll
+            for (int i = 1; i < N; ++i) bits &= window_bits(w[i], V);
+            return bits != 0u;
+        }
+    }
+    return !any_nan && fast_reject_union<N>(w, V, tiny_cull);
+}
+
 // Strip spheres.  Before a strip of an interior draw is projected vertex by vertex, it is tested
 // through a bounding sphere (c, r) of its vertices, computed once per work item in object space.
 // For a vertex v = c + d, |d| <= r, with a = (row x'')[0..2] and b = (row w)[0..2] of the draw,
@@ -771,9 +810,12 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
     };
     // window position of one vertex and the per-triangle test, for interior draws (prescaled rows,
     // no range tests) or general ones (exact transform, range tests, NaN for an undecidable vertex)
+    // clip-plane bits for strips in the kernels without strip spheres (the union-box strips, whose
+    // launches see general draws of meshes reaching past the view: many views of a large mesh)
+    constexpr bool BITS = STRIPS && !SPH;
     auto window = [&](auto interior_tag, const DrawDesc& D, const ViewDesc& V, const float* q) -> float2 {
         if constexpr (decltype(interior_tag)::value) return fast_window_prescaled(D.R, D.A + 8, q[0], q[1], q[2]);
-        else return fast_window(transform(D.A, q[0], q[1], q[2]), V);
+        else return fast_window<BITS>(transform(D.A, q[0], q[1], q[2]), V);
     };
     auto reject = [&](auto interior_tag, float2 x, float2 y, float2 z, const ViewDesc& V) -> bool {
         if constexpr (decltype(interior_tag)::value) return fast_reject_box(x, y, z, V, tiny_cull);
@@ -985,7 +1027,7 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                                 w[i] = window(tag, D, V, q[i]);
                                 if constexpr (!INTERIOR) any_nan |= __builtin_isnan(w[i].x);
                             }
-                            const bool all_out = !any_nan && fast_reject_union<TPT + 2>(w, V, tiny_cull);
+                            const bool all_out = fast_reject_strip<TPT + 2, BITS>(w, any_nan, V, tiny_cull);
                             if (any_valid) {
                                 st.add(kStTriDraws, TPT);
                                 st.add(kStStripDraws);

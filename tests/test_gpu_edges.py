@@ -171,9 +171,9 @@ def _outside_scene():
 @pytest.mark.parametrize("mode", [1, 2, 3, 4])
 def test_triangles_beyond_a_clip_plane(mode):
     """Triangles wholly beyond a side or the near plane, with vertices outside the fast stage-1
-    range (they take the exact path, which culls them: near and side culls are counted), next to
-    triangles across a side and across the near plane (rasterized, or clipped in stage 2): every
-    stage-1 mode's image equals the oracle's."""
+    range, next to triangles across a side and across the near plane (rasterized, or clipped in
+    stage 2): every stage-1 mode's image equals the oracle's.  The exact-only mode culls the
+    former in the classification (near and side culls counted)."""
     meshes, view = _outside_scene()
     ref = O.rasterize(meshes, view)
     assert (ref != O.EMPTY).sum() > 100
@@ -182,4 +182,19 @@ def test_triangles_beyond_a_clip_plane(mode):
         vis = c.rasterize_meshes(gm, view)
         assert_vis_equal(api.as_uint64(vis), ref, f"s1_mode {mode}")
         st = c.stats()
-    assert st["culled_frustum"] > 0 and st["culled_near"] > 0, st
+    if mode == 1:
+        assert st["culled_frustum"] > 0 and st["culled_near"] > 0, st
+
+
+def test_clip_plane_bits_reject_strips_before_the_exact_path():
+    """Union-box strips (s1_mode 4) whose vertices all lie beyond one clip plane are rejected from
+    the clip-plane bits of their vertices, so that few near and side culls are left for the
+    classification, against all of them with the exact path alone (s1_mode 1)."""
+    meshes, view = _outside_scene()
+    left = {}
+    for mode in (1, 4):
+        with api.Context(flags=api.FLAG_STATS, s1_mode=mode, s1_multi_tris_per_thread=4) as c:
+            c.rasterize_meshes([api.GpuMesh.from_host(m) for m in meshes], view)
+            st = c.stats()
+        left[mode] = st["culled_frustum"] + st["culled_near"]
+    assert left[1] >= 128 and 10 * left[4] < left[1], left
