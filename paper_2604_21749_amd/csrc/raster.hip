@@ -664,7 +664,27 @@ template <int N>
 struct StripEntry {
     float2 w[N];
     uint32_t draw, tri;
+    uint32_t even;                // bit k: triangle k's own vertex order is an even permutation of
+                                  // strip vertices k, k + 1, k + 2 (same winding)
 };
+
+// Provably back-facing from fast window positions p0, p1, p2 (in the strip's vertex order, `even`
+// when that order has the triangle's own winding): each fast position is within m = kFastMargin of
+// its snapped position, so the snapped signed area differs from the one of the fast positions by at
+// most 2m(|a.x| + |a.y| + |b.x| + |b.y|) + 8m^2 (a = p1 - p0, b = p2 - p0); the binary32 evaluation
+// adds at most 5u(|a.x b.y| + |a.y b.x|), bounded here by 2^-20 times that sum, and the bound's own
+// roundings are covered by the factor 1 + 2^-16.  A negative snapped area is culled in every stage,
+// so the triangle covers nothing.  NaN positions (outside the fast range) never pass.
+__device__ __forceinline__ bool fast_back_facing(float2 p0, float2 p1, float2 p2, bool even)
+{
+    const float ax = p1.x - p0.x, ay = p1.y - p0.y, bx = p2.x - p0.x, by = p2.y - p0.y;
+    const float P = ax * by, Q = ay * bx;
+    const float A = even ? P - Q : Q - P;
+    const float m = kFastMargin;
+    const float B = (2.0f * m) * ((__builtin_fabsf(ax) + __builtin_fabsf(ay)) + (__builtin_fabsf(bx) + __builtin_fabsf(by))) +
+                    8.0f * m * m + (1.0f / 1048576.0f) * (__builtin_fabsf(P) + __builtin_fabsf(Q));
+    return A < -(B * (1.0f + 1.0f / 65536.0f));
+}
 
 // A (draw, lane) pair of the stage-1 strip path whose sphere test could not reject the strip of
 // that lane of the wavefront: it waits in LDS for the union-box and per-triangle tests.
@@ -838,8 +858,10 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
             for (int k = 0; k < TPT; ++k) {
                 const bool rej = interior ? fast_reject_box(e.w[k], e.w[k + 1], e.w[k + 2], V, tiny_cull)
                                           : fast_reject(e.w[k], e.w[k + 1], e.w[k + 2], V, tiny_cull);
+                const bool back = !rej && fast_back_facing(e.w[k], e.w[k + 1], e.w[k + 2], (e.even >> k) & 1u);
                 if (have && rej) st.add(kStCulledTiny);
-                push(have && !rej, dd, e.tri + (uint32_t)k, fill_mesh);
+                if (have && back) st.add(kStCulledBack);
+                push(have && !rej && !back, dd, e.tri + (uint32_t)k, fill_mesh);
             }
         }
     };
@@ -928,6 +950,17 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                 any_valid |= valid[k];
             }
             const bool lane_strip = build_strip<TPT>(vi, sv) && all_valid;
+            // winding of each strip triangle against its own vertex order (union-box strips)
+            uint32_t even = 0;
+            if constexpr (!SPH) {
+#pragma unroll
+                for (int k = 0; k < TPT; ++k) {
+                    const uint32_t a0 = vi[k][0], a1 = vi[k][1];
+                    const bool ev = (a0 == sv[k] && a1 == sv[k + 1]) || (a0 == sv[k + 1] && a1 == sv[k + 2]) ||
+                                    (a0 == sv[k + 2] && a1 == sv[k]);
+                    even |= (uint32_t)ev << k;
+                }
+            }
             if (__ballot(!any_valid || lane_strip) == __ballot(1)) {
                 float q[TPT + 2][3];
 #pragma unroll
@@ -1043,6 +1076,7 @@ __global__ void __launch_bounds__(BLOCK) stage1_fast_kernel(RasterArgs a, CURAST
                                     for (int i = 0; i < TPT + 2; ++i) se.w[i] = w[i];
                                     se.draw = d;
                                     se.tri = tri[0];
+                                    se.even = even;
                                 }
                                 stail += (uint32_t)__popcll(m);
                                 if (stail - shead >= 64) {
