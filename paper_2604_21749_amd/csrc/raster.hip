@@ -692,7 +692,7 @@ struct StripPair {
     uint32_t draw, lane;
 };
 
-// What the sphere test reads of a draw and its view, loaded one draw ahead of its use.
+// What the sphere test reads of a draw and its view (one record, so one batch of loads per draw).
 struct SphereDraw {
     float Rx[4], Ry[4], Aw[4];
     float wnorm, slack, wmax, hmax;
